@@ -1,0 +1,243 @@
+/*
+ * cox.h -- C ABI of libcox.so, an MI355X (gfx950) library of kernels built on
+ * CUDA's 32-lane warp-level functions with their exact semantics.
+ *
+ * The paper this library follows (COX, "CUDA on X86 by Exposing Warp-Level
+ * Functions to CPUs") runs CUDA kernels that use warp shuffles, warp votes
+ * and cooperative-group tiles (its Sec. 2.2 and Table 1) on CPUs.  This
+ * library runs the same kind of kernels on AMD wave64 hardware: every
+ * 64-lane wavefront carries two logical 32-lane warps; a logical warp's
+ * ballot is one half of the wave's 64-bit lane mask.
+ *
+ * Conventions for every entry point below:
+ *  - Pointers named as device buffers point to GPU memory (hipMalloc or a
+ *    torch CUDA tensor); the caller owns all of them.  The library never
+ *    allocates on these calls.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on that stream; results are ready when the
+ *    stream is synchronized.
+ *  - Arguments are validated before anything is enqueued; on an error
+ *    nothing is launched and the status says why.  A failed HIP launch
+ *    returns COX_ERR_HIP (its hipError_t via cox_last_hip_error()).
+ *  - n = 0 is valid everywhere: totals become the identity (0 or -0.0),
+ *    counts 0, nothing else is written.
+ *  - Workspaces (`ws`, `ws_bytes`) are device buffers sized by
+ *    cox_workspace_bytes().  A fresh workspace must be zero-filled once
+ *    (cox_workspace_init); every call leaves it ready for the next call of
+ *    the same operation kind.  Calls that share a workspace must be ordered
+ *    on one stream; a workspace used for a different operation kind must be
+ *    re-initialised.
+ *  - Vector loads need 16-byte aligned data pointers for the reduce, dot,
+ *    scan, compaction and sort entry points (COX_ERR_ALIGN otherwise).
+ */
+#ifndef COX_H
+#define COX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  COX_OK = 0,
+  COX_ERR_INVALID = 1,     /* bad size, width, offset, tile or schedule */
+  COX_ERR_DTYPE = 2,       /* dtype / accumulation not offered by this entry */
+  COX_ERR_ALIGN = 3,       /* data pointer not 16-byte aligned */
+  COX_ERR_HIP = 4,         /* a HIP call failed; see cox_last_hip_error() */
+  COX_ERR_WORKSPACE = 5,   /* workspace missing or smaller than required */
+  COX_ERR_UNSUPPORTED = 6, /* schedule outside the compiled set */
+  COX_ERR_TIMEOUT = 7      /* a bounded cross-block wait gave up */
+} cox_status;
+
+typedef enum { COX_I32 = 0, COX_U32 = 1, COX_F32 = 2, COX_BF16 = 3 } cox_dtype;
+
+/* accumulation of floating-point reductions: plain binary32 adds, or the
+ * compensated TwoSum / TwoProduct variant (Ogita, Rump and Oishi's Sum2 /
+ * Dot2 carried through the warp tree) */
+typedef enum { COX_ACC_PLAIN = 0, COX_ACC_TWOSUM = 1 } cox_acc;
+
+/* warp shuffle variants (CUDA __shfl_sync, __shfl_up_sync,
+ * __shfl_down_sync, __shfl_xor_sync) */
+typedef enum { COX_SHFL_IDX = 0, COX_SHFL_UP = 1, COX_SHFL_DOWN = 2, COX_SHFL_XOR = 3 } cox_shfl_op;
+
+/* operation kinds for cox_workspace_bytes */
+typedef enum {
+  COX_OP_REDUCE = 0,
+  COX_OP_DOT = 1,
+  COX_OP_SCAN = 2,
+  COX_OP_COMPACT = 3,
+  COX_OP_SEGMENTED = 4
+} cox_op;
+
+/* Schedule sigma of the chunked kernels.  A chunk is the tile of one
+ * thread block: S = 32 * warps_per_block * items_per_lane elements.
+ * Thread (w, l) of the block owns, for row i in [0, items/V) and vector slot
+ * v in [0, V) (V = min(items, 16 bytes / element size)), chunk offset
+ *     w * 32 * items + (i * 32 + l) * V + v
+ * and accumulates its elements in (i, v) order; the warp combines lanes with
+ * the shfl_down tree (offsets 16, 8, 4, 2, 1), lane 0 of every warp puts the
+ * warp value in shared memory, and warp 0 runs the same tree over those
+ * values.  Floating-point results depend on (items_per_lane,
+ * warps_per_block) only, never on grid_blocks or on the order in which
+ * blocks run.  Zero fields select the operation's default.
+ *   items_per_lane  : 1, 2, 4, 8, 16 or 32
+ *   warps_per_block : 1, 2, 4, 8, 16 or 32
+ *   grid_blocks     : persistent grid size (0 = fill the device)
+ */
+typedef struct {
+  int32_t items_per_lane;
+  int32_t warps_per_block;
+  int32_t grid_blocks;
+  int32_t reserved;
+} cox_cfg;
+
+const char *cox_status_string(cox_status s);
+/* hipError_t of the most recent COX_ERR_HIP on the calling thread */
+int cox_last_hip_error(void);
+/* library ABI version (major * 100 + minor) */
+int cox_version(void);
+/* default schedule the library uses for `op` / `dtype` when cfg is NULL or
+ * has zero fields; writes *out */
+cox_status cox_default_cfg(cox_op op, cox_dtype dtype, cox_cfg *out);
+
+/* Bytes of workspace that `op` needs for n elements (nseg segments for
+ * COX_OP_SEGMENTED) under cfg (NULL = defaults). */
+size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, const cox_cfg *cfg);
+/* Zero-fills a workspace on `stream` (with a kernel, so it may be captured
+ * in a graph). */
+cox_status cox_workspace_init(void *ws, size_t ws_bytes, void *stream);
+/* Synchronises `stream`, then reports COX_ERR_TIMEOUT if a bounded
+ * cross-block wait of a call that used this workspace gave up since the
+ * previous check (the results of that call are invalid), and clears the
+ * flag.  COX_OK otherwise. */
+cox_status cox_workspace_status(void *ws, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Warp functions applied to arrays (the paper's warp builtins operating
+ * on per-warp arrays, Sec. 3.2; semantics per the CUDA Programming Guide
+ * that the paper refers to in Sec. 2.2.1).
+ * ------------------------------------------------------------------- */
+
+/* For every 32-element warp g (n % 32 == 0): the lanes l set in mask[g]
+ * (mask == NULL: all 32) execute
+ *     out[32g + l] = shfl_op(v, arg_l, width)
+ * with arg_l = argv[32g + l] when argv != NULL, else arg, and the CUDA
+ * rules: b = l & ~(width-1); IDX reads b + (arg & (width-1)); UP reads
+ * l - arg if l - b >= arg else keeps v[l]; DOWN reads l + arg if
+ * l - b + arg < width else keeps v[l]; XOR reads j = l ^ arg if
+ * j < b + width (an earlier segment is readable) else keeps v[l].
+ * Lanes outside the mask copy v.  width is 1, 2, 4, 8, 16 or 32; arg of
+ * UP / DOWN / XOR is in [0, 31].  A source lane outside the mask is
+ * undefined in CUDA; here it reads that lane's input.
+ * v, out, argv, mask: device buffers (int32[n], int32[n], int32[n],
+ * uint32[n/32]). */
+cox_status cox_warp_shfl(const int32_t *v, int32_t *out, int64_t n, int op, int32_t arg,
+                         const int32_t *argv, int width, const uint32_t *mask, void *stream);
+
+/* For every warp g (n % 32 == 0) the lanes of m = mask[g] (NULL: all)
+ * execute b = __ballot_sync(m, pred), a = __any_sync(m, pred),
+ * t = __all_sync(m, pred) (pred nonzero = true); the lowest lane of m
+ * stores ballot[g] = b, anyall[g] = a | t << 1 (zeros for an empty mask).
+ * Code 4 of the paper (VoteAll) is the case pred = tx % 2, full mask.
+ * pred: int32[n]; mask: uint32[n/32] or NULL; ballot: uint32[n/32];
+ * anyall: int32[n/32]; all device buffers. */
+cox_status cox_warp_vote(const int32_t *pred, const uint32_t *mask, int64_t n, uint32_t *ballot,
+                         int32_t *anyall, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Block reduction with warp shuffles (Sec. 2.3 Code 1 generalised to a
+ * 256-thread block, the SDK reduction kernels of Table 1).
+ * ------------------------------------------------------------------- */
+
+/* 256-thread blocks of 8 logical warps, one element per thread:
+ *   block_sums[b] = wrap32 sum of x[256b .. 256b+255] (shfl_down tree per
+ *                   warp, shared-memory combine of the 8 warp values);
+ *   warp_pos_count[g] = popc(__ballot_sync(FULL, x > 0)) over
+ *                   x[32g .. 32g+31].
+ * Elements past n count as 0 and as not positive.
+ * x: int32[n]; block_sums: int32[ceil(n/256)];
+ * warp_pos_count: int32[ceil(n/32)]; device buffers. */
+cox_status cox_warp_reduce_blocks_i32(const int32_t *x, int64_t n, int32_t *block_sums,
+                                      int32_t *warp_pos_count, void *stream);
+
+/* Chunked sum of x under schedule cfg (see cox_cfg).
+ * dtype COX_I32 (acc must be PLAIN): lanes, warps and blocks add with
+ *   two's-complement wrap (CUDA int); chunk partials are int32;
+ *   *total (int64) = sum of the chunk partials as int64, which equals the
+ *   exact sum whenever no chunk partial overflows.
+ * dtype COX_F32 / COX_BF16 (bfloat16 bits as uint16, widened exactly):
+ *   binary32 lane accumulation and tree (TwoSum-compensated pairs (s, c)
+ *   for COX_ACC_TWOSUM), chunk partials float32 (float32 pairs for
+ *   TWOSUM), and *total (double) = FP64 final combine: a fixed tree shaped
+ *   like a 256-thread block (thread j adds chunks j, j+256, ... serially
+ *   from -0.0, an FP64 shfl_down tree per warp, then over the 8 warp
+ *   values); for TWOSUM each chunk enters as (double)s + (double)c.
+ * Elements past n are padding equal to -0.0 (0 for int32).
+ * x: device buffer of n elements; chunk_partials: device buffer of
+ * nchunks (x2 for TWOSUM) entries or NULL; total: device int64 / double;
+ * ws: workspace of cox_workspace_bytes(COX_OP_REDUCE, ...). */
+cox_status cox_warp_reduce(const void *x, cox_dtype dtype, int64_t n, cox_acc acc,
+                           const cox_cfg *cfg, void *chunk_partials, void *total, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Chunked dot product sum_i a_i * b_i (dtype COX_F32 or COX_BF16) with the
+ * schedule of cox_warp_reduce.  PLAIN: s = fmaf(a_i, b_i, s) per element.
+ * TWOSUM (Dot2): (p, pe) = TwoProduct(a_i, b_i) = (a*b, fmaf(a, b, -p)),
+ * (s, q) = TwoSum(s, p), c = c + (pe + q).  Padding: a = -0.0, b = +0.0.
+ * Result in *total (device double); partials as for cox_warp_reduce. */
+cox_status cox_warp_dot(const void *a, const void *b, cox_dtype dtype, int64_t n, cox_acc acc,
+                        const cox_cfg *cfg, void *chunk_partials, double *total, void *ws,
+                        size_t ws_bytes, void *stream);
+
+/* Inclusive int32 scan, y_i = (x_0 + ... + x_i) mod 2^32, in one pass:
+ * warp scans with shfl_up (Kogge-Stone), warp totals combined in shared
+ * memory, chunks chained by decoupled look-back (status words published
+ * with device-scope atomics; chunk order from a ticket counter so that a
+ * chunk only waits for chunks already being processed).  x, y: int32[n]
+ * device buffers (may not overlap); ws: cox_workspace_bytes(COX_OP_SCAN). */
+cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg *cfg, void *ws,
+                         size_t ws_bytes, void *stream);
+
+/* Stable compaction keeping x_i > 0: out[0 .. *count) = the kept elements
+ * in input order; *count (device int64) = their number.  Per warp and row
+ * the ranks come from ballots: rank = popc(ballot & lanemask_lt) summed
+ * over the lane's vector slots; warp counts are scanned in shared memory
+ * and chunk offsets chained by decoupled look-back.  x: int32[n]; out:
+ * int32[n] capacity; ws: cox_workspace_bytes(COX_OP_COMPACT). */
+cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t *count,
+                              const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
+
+/* Sorts every group of `tile` = 32 consecutive keys ascending (unsigned)
+ * with a bitonic network whose cross-lane steps are __shfl_xor_sync
+ * exchanges inside the group (cfg->items_per_lane keys per lane, 1 to 16;
+ * 0 = default).  A partial last group is sorted among its valid keys.
+ * keys, out: uint32[n] device buffers (may be the same buffer). */
+cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
+                         const cox_cfg *cfg, void *stream);
+
+/* thread_block_tile<T> reduction: out[g] = wrap32 sum of x[gT .. gT+T-1]
+ * computed with tile.shfl_down(v, o), o = T/2 .. 1, one element per lane;
+ * T in {2, 4, 8, 16, 32}; elements past n count as 0.
+ * x: int32[n]; out: int32[ceil(n/T)]; device buffers. */
+cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, void *stream);
+
+/* Masked (divergent) warp operations with predicate-derived masks, n % 32
+ * == 0.  Lane l of warp g, x = x[32g + l]:
+ *   p = ((uint32)x & 1023) < density;  m = __ballot_sync(FULL, p);
+ *   if (p) { b = __ballot_sync(m, x > 0); A = __any_sync(m, ((x >> 10) & 31) == 0);
+ *            L = __all_sync(m, ((x >> 15) & 31) != 0);
+ *            s = __shfl_sync(m, x, next lane of m above l, wrapping);
+ *            bc = __shfl_sync(m, x, ffs(m) - 1);  out = s;
+ *            lane ffs(m)-1 stores rec[g] = {m, b, A | L << 1, bc}; }
+ *   else out = INT32_MIN;   (m == 0: lane 0 stores rec[g] = {0, 0, 0, 0})
+ * density in [0, 1024].  x, out: int32[n]; rec: uint32[4 * n/32]. */
+cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *out, uint32_t *rec,
+                           void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COX_H */

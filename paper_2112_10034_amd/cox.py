@@ -1,0 +1,302 @@
+"""Thin ctypes binding over libcox.so (the C ABI declared in include/cox.h).
+
+Every function here only marshals arguments: it checks tensor dtype, device
+and contiguity, allocates outputs and workspaces with torch (device memory
+plumbing), passes raw device pointers and torch's current HIP stream to the
+C entry point of the same name, and raises ``CoxError`` on a nonzero
+status.  All computation happens in the library's HIP kernels; there is no
+CPU fallback.  If libcox.so has not been built, loading raises.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcox.so")
+
+I32, U32, F32, BF16 = 0, 1, 2, 3
+PLAIN, TWOSUM = 0, 1
+SHFL_IDX, SHFL_UP, SHFL_DOWN, SHFL_XOR = 0, 1, 2, 3
+OP_REDUCE, OP_DOT, OP_SCAN, OP_COMPACT, OP_SEGMENTED = 0, 1, 2, 3, 4
+
+ERR_TIMEOUT = 7
+
+
+class CoxError(RuntimeError):
+    def __init__(self, code, what, lib=None):
+        msg = f"{what}: status {code}"
+        if lib is not None:
+            msg += f" ({lib.cox_status_string(code).decode()})"
+            if code == 4:
+                msg += f", hipError {lib.cox_last_hip_error()}"
+        super().__init__(msg)
+        self.code = code
+
+
+class cox_cfg(C.Structure):
+    _fields_ = [("items_per_lane", C.c_int32), ("warps_per_block", C.c_int32),
+                ("grid_blocks", C.c_int32), ("reserved", C.c_int32)]
+
+
+_lib = None
+
+_P, _I64, _I, _SZ = C.c_void_p, C.c_int64, C.c_int, C.c_size_t
+_SIGS = {
+    "cox_status_string": (C.c_char_p, [_I]),
+    "cox_last_hip_error": (_I, []),
+    "cox_version": (_I, []),
+    "cox_default_cfg": (_I, [_I, _I, C.POINTER(cox_cfg)]),
+    "cox_workspace_bytes": (_SZ, [_I, _I, _I64, _I64, C.POINTER(cox_cfg)]),
+    "cox_workspace_init": (_I, [_P, _SZ, _P]),
+    "cox_workspace_status": (_I, [_P, _P]),
+    "cox_warp_shfl": (_I, [_P, _P, _I64, _I, C.c_int32, _P, _I, _P, _P]),
+    "cox_warp_vote": (_I, [_P, _P, _I64, _P, _P, _P]),
+    "cox_warp_reduce_blocks_i32": (_I, [_P, _I64, _P, _P, _P]),
+    "cox_warp_reduce": (_I, [_P, _I, _I64, _I, C.POINTER(cox_cfg), _P, _P, _P, _SZ, _P]),
+    "cox_warp_dot": (_I, [_P, _P, _I, _I64, _I, C.POINTER(cox_cfg), _P, _P, _P, _SZ, _P]),
+    "cox_warp_scan": (_I, [_P, _P, _I64, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_ballot_compact": (_I, [_P, _I64, _P, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_tile_sort": (_I, [_P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
+    "cox_tile_reduce": (_I, [_P, _I64, _I, _P, _P]),
+    "cox_warp_masked": (_I, [_P, _I64, _I, _P, _P, _P]),
+}
+
+
+def lib():
+    """Loads libcox.so once; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no CPU fallback)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(code, what):
+    if code != 0:
+        raise CoxError(code, what, lib())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _dtype_code(t):
+    if t.dtype == torch.int32:
+        return I32
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def make_cfg(items_per_lane=0, warps_per_block=0, grid_blocks=0):
+    return cox_cfg(int(items_per_lane), int(warps_per_block), int(grid_blocks), 0)
+
+
+def _cfgp(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, (tuple, list)):
+        cfg = make_cfg(*cfg)
+    return C.byref(cfg)
+
+
+def default_cfg(op, dtype=I32):
+    c = cox_cfg()
+    _check(lib().cox_default_cfg(op, dtype, C.byref(c)), "cox_default_cfg")
+    return (c.items_per_lane, c.warps_per_block, c.grid_blocks)
+
+
+# ---------------------------------------------------------------- workspaces
+class Workspace:
+    """A zero-initialised device workspace owned by the caller."""
+
+    def __init__(self, nbytes, device=None):
+        nbytes = max(256, (int(nbytes) + 255) // 256 * 256)
+        self.tensor = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+        self.nbytes = nbytes
+        _check(lib().cox_workspace_init(_ptr(self.tensor), nbytes, _stream()), "cox_workspace_init")
+
+    def status(self):
+        """Synchronises the stream; raises CoxError(COX_ERR_TIMEOUT) if a
+        bounded cross-block wait gave up since the last check."""
+        _check(lib().cox_workspace_status(_ptr(self.tensor), _stream()), "cox_workspace_status")
+
+
+_ws_cache = {}
+
+
+def workspace(op, dtype, n, nseg=0, cfg=None, device=None):
+    """Per-(op, device) cached workspace large enough for this call."""
+    need = lib().cox_workspace_bytes(op, dtype, int(n), int(nseg), _cfgp(cfg))
+    if need == 0:
+        raise CoxError(1, "cox_workspace_bytes", lib())
+    dev = torch.device(device or "cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    key = (op, dev.index)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.nbytes < need:
+        ws = Workspace(need, dev)
+        _ws_cache[key] = ws
+    return ws
+
+
+# ---------------------------------------------------------------- entry points
+def warp_shfl(v, op, arg=0, width=32, mask=None, argv=None, out=None):
+    _need(v, torch.int32, "v")
+    n = v.numel()
+    out = torch.empty_like(v) if out is None else out
+    if mask is not None:
+        _need(mask, torch.int32, "mask")  # uint32 bits carried in int32
+    if argv is not None:
+        _need(argv, torch.int32, "argv")
+    _check(lib().cox_warp_shfl(_ptr(v), _ptr(out), n, int(op), int(arg), _ptr(argv), int(width),
+                               _ptr(mask), _stream()), "cox_warp_shfl")
+    return out
+
+
+def warp_vote(pred, mask=None):
+    _need(pred, torch.int32, "pred")
+    g = pred.numel() // 32
+    bal = torch.zeros(g, dtype=torch.int32, device=pred.device)
+    aa = torch.zeros(g, dtype=torch.int32, device=pred.device)
+    if mask is not None:
+        _need(mask, torch.int32, "mask")
+    _check(lib().cox_warp_vote(_ptr(pred), _ptr(mask), pred.numel(), _ptr(bal), _ptr(aa), _stream()),
+           "cox_warp_vote")
+    return bal, aa
+
+
+def warp_reduce_blocks_i32(x, block_sums=None, warp_pos_count=None):
+    _need(x, torch.int32, "x")
+    n = x.numel()
+    if block_sums is None:
+        block_sums = torch.empty((n + 255) // 256, dtype=torch.int32, device=x.device)
+    if warp_pos_count is None:
+        warp_pos_count = torch.empty((n + 31) // 32, dtype=torch.int32, device=x.device)
+    _check(lib().cox_warp_reduce_blocks_i32(_ptr(x), n, _ptr(block_sums), _ptr(warp_pos_count), _stream()),
+           "cox_warp_reduce_blocks_i32")
+    return block_sums, warp_pos_count
+
+
+def _nchunks(n, cfg, op, dt):
+    k, W, _ = cfg if isinstance(cfg, (tuple, list)) else (
+        (cfg.items_per_lane, cfg.warps_per_block, cfg.grid_blocks) if cfg is not None else (0, 0, 0))
+    dk, dW, _ = default_cfg(op, dt)
+    k, W = k or dk, W or dW
+    S = 32 * W * k
+    return (n + S - 1) // S
+
+
+def warp_reduce(x, acc=PLAIN, cfg=None, partials=True, total=None, partials_out=None):
+    """Returns (total, chunk_partials or None) as device tensors: total is
+    int64 for int32 input, float64 otherwise."""
+    dt = _dtype_code(x)
+    _need(x, x.dtype, "x")
+    n = x.numel()
+    if total is None:
+        total = torch.empty(1, dtype=torch.int64 if dt == I32 else torch.float64, device=x.device)
+    part = partials_out
+    if part is None and partials:
+        nch = _nchunks(n, cfg, OP_REDUCE, dt)
+        shape = (nch, 2) if acc == TWOSUM else (nch,)
+        part = torch.empty(shape, dtype=torch.int32 if dt == I32 else torch.float32, device=x.device)
+    ws = workspace(OP_REDUCE, dt, n, cfg=cfg, device=x.device)
+    _check(lib().cox_warp_reduce(_ptr(x), dt, n, int(acc), _cfgp(cfg), _ptr(part), _ptr(total),
+                                 _ptr(ws.tensor), ws.nbytes, _stream()), "cox_warp_reduce")
+    return total, part
+
+
+def warp_dot(a, b, acc=PLAIN, cfg=None, partials=True, total=None, partials_out=None):
+    dt = _dtype_code(a)
+    _need(a, a.dtype, "a")
+    _need(b, a.dtype, "b")
+    if a.numel() != b.numel():
+        raise ValueError("a and b differ in size")
+    n = a.numel()
+    if total is None:
+        total = torch.empty(1, dtype=torch.float64, device=a.device)
+    part = partials_out
+    if part is None and partials:
+        nch = _nchunks(n, cfg, OP_DOT, dt)
+        shape = (nch, 2) if acc == TWOSUM else (nch,)
+        part = torch.empty(shape, dtype=torch.float32, device=a.device)
+    ws = workspace(OP_DOT, dt, n, cfg=cfg, device=a.device)
+    _check(lib().cox_warp_dot(_ptr(a), _ptr(b), dt, n, int(acc), _cfgp(cfg), _ptr(part), _ptr(total),
+                              _ptr(ws.tensor), ws.nbytes, _stream()), "cox_warp_dot")
+    return total, part
+
+
+def warp_scan(x, cfg=None, out=None):
+    _need(x, torch.int32, "x")
+    n = x.numel()
+    y = torch.empty_like(x) if out is None else out
+    ws = workspace(OP_SCAN, I32, n, cfg=cfg, device=x.device)
+    _check(lib().cox_warp_scan(_ptr(x), _ptr(y), n, _cfgp(cfg), _ptr(ws.tensor), ws.nbytes, _stream()),
+           "cox_warp_scan")
+    return y
+
+
+def ballot_compact(x, cfg=None, out=None, count=None):
+    """Returns (out buffer of capacity n, count as a 1-element int64 device
+    tensor); the kept elements are out[:count]."""
+    _need(x, torch.int32, "x")
+    n = x.numel()
+    out = torch.empty_like(x) if out is None else out
+    count = torch.empty(1, dtype=torch.int64, device=x.device) if count is None else count
+    ws = workspace(OP_COMPACT, I32, n, cfg=cfg, device=x.device)
+    _check(lib().cox_ballot_compact(_ptr(x), n, _ptr(out), _ptr(count), _cfgp(cfg), _ptr(ws.tensor),
+                                    ws.nbytes, _stream()), "cox_ballot_compact")
+    return out, count
+
+
+def tile_sort(keys, tile=32, cfg=None, out=None):
+    """keys: int32 tensor holding uint32 bit patterns (sorted as unsigned)."""
+    _need(keys, torch.int32, "keys")
+    out = torch.empty_like(keys) if out is None else out
+    _check(lib().cox_tile_sort(_ptr(keys), _ptr(out), keys.numel(), int(tile), _cfgp(cfg), _stream()),
+           "cox_tile_sort")
+    return out
+
+
+def tile_reduce(x, tile, out=None):
+    _need(x, torch.int32, "x")
+    n = x.numel()
+    out = torch.empty((n + tile - 1) // tile, dtype=torch.int32, device=x.device) if out is None else out
+    _check(lib().cox_tile_reduce(_ptr(x), n, int(tile), _ptr(out), _stream()), "cox_tile_reduce")
+    return out
+
+
+def warp_masked(x, density, out=None, rec=None):
+    _need(x, torch.int32, "x")
+    n = x.numel()
+    out = torch.empty_like(x) if out is None else out
+    rec = torch.empty((n // 32, 4), dtype=torch.int32, device=x.device) if rec is None else rec
+    _check(lib().cox_warp_masked(_ptr(x), n, int(density), _ptr(out), _ptr(rec), _stream()),
+           "cox_warp_masked")
+    return out, rec

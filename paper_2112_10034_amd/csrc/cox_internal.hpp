@@ -1,0 +1,81 @@
+// Host/device helpers shared by the library's HIP sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/cox.h"
+#include "cox_warp.hpp"
+
+namespace cox {
+
+// ---------------------------------------------------------------- workspace
+// First 256 bytes: header words; data (status words / partials) follows.
+enum : int { HDR_TICKET = 0, HDR_EPOCH = 1, HDR_DONE = 2, HDR_ERR = 3, HDR_WORDS = 64 };
+constexpr size_t WS_HEADER = 256;
+
+// look-back status word: [tag:30][flag:2][value:32]
+enum : uint32_t { ST_AGG = 1, ST_PREFIX = 2 };
+constexpr uint32_t TAG_MOD = (1u << 30) - 1;
+__host__ __device__ __forceinline__ uint32_t tag_of_epoch(uint32_t e) { return 1u + e % TAG_MOD; }
+__device__ __forceinline__ uint64_t st_pack(uint32_t tag, uint32_t flag, uint32_t v) {
+  return ((uint64_t)tag << 34) | ((uint64_t)flag << 32) | v;
+}
+__device__ __forceinline__ uint32_t st_tag(uint64_t s) { return (uint32_t)(s >> 34); }
+__device__ __forceinline__ uint32_t st_flag(uint64_t s) { return (uint32_t)(s >> 32) & 3u; }
+__device__ __forceinline__ uint32_t st_val(uint64_t s) { return (uint32_t)s; }
+
+// device-scope (all XCDs) relaxed atomics: on gfx950 these are sc1
+// loads/stores that bypass the per-XCD L2's non-coherent copies
+__device__ __forceinline__ uint64_t ld_dev(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_dev32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t add_dev32(uint32_t *p, uint32_t v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The call's epoch, read with acquire ordering before the block draws any
+// ticket (the block that resets the epoch does so after every block has
+// drawn its last ticket).
+__device__ __forceinline__ uint32_t ld_epoch(const uint32_t *hdr) {
+  return __hip_atomic_load(&hdr[HDR_EPOCH], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// spin bound of every cross-block wait (well under a second); a wait that
+// runs out, or that sees another wait's failure, sets HDR_ERR and proceeds,
+// so no kernel can hang
+constexpr uint32_t MAX_SPIN = 1u << 20;
+
+// non-temporal 16-byte store (streaming output that no later kernel of the
+// call reads back)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_stream4(void *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+  u32x4 v = {a, b, c, d};
+  __builtin_nontemporal_store(v, (u32x4 *)p);
+}
+
+// ---------------------------------------------------------------- host side
+void set_hip_error(hipError_t e);
+cox_status launch_status();                      // hipGetLastError -> status
+int device_cus();                                // compute units of the current device
+int blocks_per_cu(const void *kernel, int block);  // occupancy, cached per (kernel, block)
+int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested);
+
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+inline bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+// resolved schedule
+struct Sigma {
+  int k, W, G;
+};
+cox_status resolve_cfg(cox_op op, cox_dtype dt, const cox_cfg *cfg, Sigma *out);
+
+}  // namespace cox

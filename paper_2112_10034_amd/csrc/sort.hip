@@ -1,0 +1,158 @@
+// 32-key bitonic tile sort.
+//
+// A group of 32 consecutive keys lives in LG = 32/K consecutive lanes of a
+// logical warp, K keys per lane (lane g of the group holds keys gK..gK+K-1,
+// loaded as one vector), so key index i = g*K + r.  The network is the
+// bitonic sorter in its all-ascending form: for each merge size k2 = 2, 4,
+// .., 32 a first layer compares i with i ^ (k2 - 1) (the mirror inside the
+// k2-block), then half-cleaner layers compare i with i ^ j for j = k2/4 ..
+// 1; the smaller index always keeps the minimum.  A layer whose partner
+// differs only in the low log2(K) bits is a compare-exchange between two
+// registers of one lane; every other layer is a __shfl_xor_sync inside the
+// group (partner lane g ^ (mask / K), register r ^ (mask mod K)) followed by
+// min or max.  With K = 4 all cross-lane layers are DPP quad_perm /
+// row_half_mirror exchanges.  The sorted result is the unique ascending
+// order, so any such network gives the same output as the one-key-per-lane
+// network.
+#include "cox_internal.hpp"
+
+namespace cox {
+
+template <int K, int PM, int LB>
+__device__ __forceinline__ void cx_layer(uint32_t (&key)[K], int g) {
+  constexpr int RM = PM & (K - 1);  // register part of the partner mask
+  constexpr int LM = PM / K;        // lane part
+  if constexpr (LM == 0) {
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+      const int r2 = r ^ RM;
+      if (r < r2) {
+        const uint32_t a = key[r], b = key[r2];
+        key[r] = a < b ? a : b;
+        key[r2] = a < b ? b : a;
+      }
+    }
+  } else {
+    uint32_t other[K];
+#pragma unroll
+    for (int r = 0; r < K; r++) other[r] = (uint32_t)xor_lane<LM>((int)key[r ^ RM]);
+    const bool lower = (g & (LB / K)) == 0;
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+      const uint32_t mn = key[r] < other[r] ? key[r] : other[r];
+      const uint32_t mx = key[r] < other[r] ? other[r] : key[r];
+      key[r] = lower ? mn : mx;
+    }
+  }
+}
+
+template <int K, int K2, int J>
+__device__ __forceinline__ void half_cleaners(uint32_t (&key)[K], int g) {
+  if constexpr (J >= 1) {
+    cx_layer<K, J, J>(key, g);
+    half_cleaners<K, K2, J / 2>(key, g);
+  }
+}
+
+template <int K, int K2>
+__device__ __forceinline__ void merge_stages(uint32_t (&key)[K], int g) {
+  if constexpr (K2 <= 32) {
+    cx_layer<K, K2 - 1, K2 / 2>(key, g);  // mirror layer
+    half_cleaners<K, K2, K2 / 4>(key, g);
+    merge_stages<K, K2 * 2>(key, g);
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void load_keys(const uint32_t *__restrict__ p, uint32_t (&key)[K]) {
+  if constexpr (K % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < K / 4; q++) {
+      const uint4 v = ((const uint4 *)p)[q];
+      key[4 * q] = v.x; key[4 * q + 1] = v.y; key[4 * q + 2] = v.z; key[4 * q + 3] = v.w;
+    }
+  } else if constexpr (K == 2) {
+    const uint2 v = *(const uint2 *)p;
+    key[0] = v.x; key[1] = v.y;
+  } else {
+    key[0] = *p;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void store_keys(uint32_t *__restrict__ p, const uint32_t (&key)[K]) {
+  if constexpr (K % 4 == 0) {
+#pragma unroll
+    for (int q = 0; q < K / 4; q++)
+      st_stream4(p + 4 * q, key[4 * q], key[4 * q + 1], key[4 * q + 2], key[4 * q + 3]);
+  } else if constexpr (K == 2) {
+    *(uint2 *)p = make_uint2(key[0], key[1]);
+  } else {
+    *p = key[0];
+  }
+}
+
+// grid-stride over lane vectors; every 32-key group is held by LG lanes of
+// one logical warp (groups never straddle a warp since 32 | 32K).  keys and
+// out may be the same buffer (each lane writes back only the positions it
+// read, after its whole group has been sorted).
+template <int K>
+__global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n) {
+  constexpr int LG = 32 / K;
+  const int g = (int)(threadIdx.x % LG);
+  const int64_t nvec = (n + K - 1) / K;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // the whole block iterates together so that partial groups see full warps
+  const int64_t rounds = (nvec + stride - 1) / stride;
+  for (int64_t it = 0; it < rounds; it++) {
+    const int64_t vi = it * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e0 = vi * K;
+    uint32_t key[K];
+    if (e0 + K <= n) {
+      load_keys<K>(keys + e0, key);
+    } else {
+#pragma unroll
+      for (int r = 0; r < K; r++) key[r] = e0 + r < n ? keys[e0 + r] : 0xffffffffu;
+    }
+    merge_stages<K, 2>(key, g);
+    if (e0 + K <= n) {
+      store_keys<K>(out + e0, key);
+    } else {
+#pragma unroll
+      for (int r = 0; r < K; r++)
+        if (e0 + r < n) out[e0 + r] = key[r];
+    }
+  }
+}
+
+using sort_fn = void (*)(const uint32_t *, uint32_t *, int64_t);
+static sort_fn pick_sort(int k) {
+  switch (k) {
+  case 1: return k_tile_sort<1>;
+  case 2: return k_tile_sort<2>;
+  case 4: return k_tile_sort<4>;
+  case 8: return k_tile_sort<8>;
+  case 16: return k_tile_sort<16>;
+  }
+  return nullptr;
+}
+
+}  // namespace cox
+
+using namespace cox;
+
+extern "C" cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
+                                    const cox_cfg *cfg, void *stream) {
+  if (n < 0 || tile != 32) return COX_ERR_INVALID;
+  const int k = (cfg && cfg->items_per_lane) ? cfg->items_per_lane : 4;
+  if (cfg && cfg->grid_blocks < 0) return COX_ERR_INVALID;
+  sort_fn fn = pick_sort(k);
+  if (!fn) return k > 0 && k <= 32 && (k & (k - 1)) == 0 ? COX_ERR_UNSUPPORTED : COX_ERR_INVALID;
+  if (n == 0) return COX_OK;
+  if (!keys || !out) return COX_ERR_INVALID;
+  if (!aligned16(keys) || !aligned16(out)) return COX_ERR_ALIGN;
+  const int64_t nvec = (n + k - 1) / k;
+  const int grid = persistent_grid((const void *)fn, 256, (nvec + 255) / 256, cfg ? cfg->grid_blocks : 0);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, out, n);
+  return launch_status();
+}

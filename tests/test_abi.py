@@ -1,0 +1,83 @@
+"""C-ABI checks that need no GPU: libcox.so loads, exports every entry point
+that include/cox.h declares, and rejects bad arguments on the host before
+launching anything."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cox.h")
+LIB = os.path.join(ROOT, "paper_2112_10034_amd", "libcox.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cox_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def cox():
+    if not os.path.exists(LIB):
+        import __graft_entry__
+
+        __graft_entry__.build()
+    from paper_2112_10034_amd import cox as binding
+
+    return binding
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for must in ["cox_warp_reduce", "cox_warp_scan", "cox_ballot_compact", "cox_tile_sort",
+                 "cox_tile_reduce", "cox_warp_masked", "cox_warp_dot", "cox_warp_shfl",
+                 "cox_warp_vote", "cox_warp_reduce_blocks_i32"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(cox):
+    lib = C.CDLL(cox.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared entry points
+    assert set(cox.exported_symbols()) <= set(declared_functions())
+
+
+def test_host_only_queries(cox):
+    L = cox.lib()
+    assert L.cox_version() >= 100
+    assert L.cox_status_string(0) == b"ok"
+    assert b"aligned" in L.cox_status_string(3)
+    k, W, G = cox.default_cfg(cox.OP_SCAN)
+    assert k in (1, 2, 4, 8, 16, 32) and W in (1, 2, 4, 8, 16, 32) and G == 0
+    n = 1 << 20
+    S = 32 * W * k
+    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n, 0, None) == 256 + 8 * (-(-n // S) + 1)
+    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, -1, 0, None) == 0
+    bad = cox.make_cfg(3, 8)
+    assert L.cox_workspace_bytes(cox.OP_REDUCE, cox.F32, n, 0, C.byref(bad)) == 0
+
+
+def test_invalid_arguments_rejected_before_launch(cox):
+    L = cox.lib()
+    # negative sizes, bad widths / tiles / ops, missing workspace: no launch happens
+    assert L.cox_warp_shfl(None, None, -32, 0, 0, None, 32, None, None) == 1
+    assert L.cox_warp_shfl(None, None, 33, 0, 0, None, 32, None, None) == 1
+    assert L.cox_warp_shfl(None, None, 32, 0, 0, None, 3, None, None) == 1
+    assert L.cox_warp_shfl(None, None, 32, 2, 32, None, 32, None, None) == 1
+    assert L.cox_warp_shfl(None, None, 32, 7, 0, None, 32, None, None) == 1
+    assert L.cox_tile_reduce(None, 64, 3, None, None) == 1
+    assert L.cox_tile_sort(None, None, 64, 16, None, None) == 1
+    assert L.cox_warp_masked(None, 33, 512, None, None, None) == 1
+    assert L.cox_warp_masked(None, 64, 2000, None, None, None) == 1
+    assert L.cox_warp_reduce(None, cox.I32, 10, cox.TWOSUM, None, None, C.c_void_p(8), None, 0, None) == 2
+    assert L.cox_warp_dot(None, None, cox.I32, 10, 0, None, None, C.c_void_p(8), None, 0, None) == 2
+    assert L.cox_warp_scan(None, None, -1, None, None, 0, None) == 1
+    # misaligned data pointer
+    assert L.cox_warp_scan(C.c_void_p(4), C.c_void_p(16), 100, None, C.c_void_p(256), 10**6, None) == 3
+    # workspace too small
+    assert L.cox_warp_scan(C.c_void_p(16), C.c_void_p(16), 100, None, C.c_void_p(256), 8, None) == 5
+    bad = cox.make_cfg(3, 8)
+    assert L.cox_warp_scan(C.c_void_p(16), C.c_void_p(16), 100, C.byref(bad), None, 0, None) == 1

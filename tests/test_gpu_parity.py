@@ -1,0 +1,262 @@
+"""GPU parity: every HIP entry point against the CPU oracle, element by
+element on the same seeded inputs.  Integer results and same-schedule FP32
+results must be bit-exact; the schedule (items_per_lane, warps_per_block) is
+passed to both sides.  Sizes span several chunks plus a ragged tail."""
+import numpy as np
+import pytest
+
+from paper_2112_10034_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SIGMAS = [(1, 1), (2, 4), (4, 8), (8, 2), (16, 8), (32, 4), (16, 16), (4, 32)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2112_10034_amd import cox
+
+    cox.lib()
+    return torch, cox
+
+
+def up(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def down(t):
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------- warp builtins
+def test_shfl_all_ops_widths_args(dev, oracle_mod):
+    torch, cox = dev
+    rng = np.random.default_rng(1)
+    v = rng.integers(-2**31, 2**31, size=32 * 8, dtype=np.int64).astype(np.int32)
+    vg = up(torch, v)
+    for op in range(4):
+        for w in (1, 2, 4, 8, 16, 32):
+            for arg in range(32):
+                got = down(cox.warp_shfl(vg, op, arg, w))
+                want = oracle_mod.warp_shfl(v, op, arg, w)
+                assert np.array_equal(got, want), (op, w, arg)
+
+
+def test_shfl_per_lane_args_and_masks(dev, oracle_mod):
+    torch, cox = dev
+    rng = np.random.default_rng(2)
+    n = 32 * 512
+    v = rng.integers(-2**31, 2**31, size=n, dtype=np.int64).astype(np.int32)
+    for op in range(4):
+        for w in (4, 32):
+            argv = (rng.integers(-100, 100, size=n) if op == 0 else rng.integers(0, 32, size=n)).astype(np.int32)
+            got = down(cox.warp_shfl(up(torch, v), op, 0, w, argv=up(torch, argv)))
+            want = oracle_mod.warp_shfl(v, op, 0, w, argv=argv)
+            assert np.array_equal(got, want), (op, w)
+    # masked broadcast from a lane inside the mask
+    masks = rng.integers(1, 2**32, size=n // 32, dtype=np.uint64).astype(np.uint32)
+    srcl = np.array([int(m & -m).bit_length() - 1 for m in masks.tolist()], np.int32)
+    argv = np.repeat(srcl, 32)
+    got = down(cox.warp_shfl(up(torch, v), 0, 0, 32, mask=up(torch, masks.view(np.int32)), argv=up(torch, argv)))
+    want = oracle_mod.warp_shfl(v, 0, 0, 32, mask=masks, argv=argv)
+    assert np.array_equal(got, want)
+
+
+def test_votes_random_masks(dev, oracle_mod):
+    torch, cox = dev
+    rng = np.random.default_rng(3)
+    n = 32 * 4096
+    pred = (rng.random(n) < 0.5).astype(np.int32) * rng.integers(1, 100, n).astype(np.int32)
+    masks = rng.integers(0, 2**32, size=n // 32, dtype=np.uint64).astype(np.uint32)
+    masks[:5] = [0, 1, 0x80000000, 0xFFFFFFFF, 0xAAAAAAAA]
+    gb, ga = cox.warp_vote(up(torch, pred), up(torch, masks.view(np.int32)))
+    wb, wa = oracle_mod.warp_vote(pred, masks)
+    assert np.array_equal(down(gb).view(np.uint32), wb)
+    assert np.array_equal(down(ga), wa)
+
+
+def test_paper_code1_and_code4_on_gpu(dev):
+    torch, cox = dev
+    val = torch.ones(32 * 4, dtype=torch.int32, device="cuda")
+    for off in (16, 8, 4, 2, 1):
+        val = val + cox.warp_shfl(val, cox.SHFL_DOWN, off)
+    assert torch.all(val == 32)
+    pred = torch.arange(256, dtype=torch.int32, device="cuda") % 2
+    bal, aa = cox.warp_vote(pred)
+    assert torch.all(((aa >> 1) & 1) == 0) and torch.all((aa & 1) == 1)
+    assert np.all(down(bal).view(np.uint32) == 0xAAAAAAAA)
+
+
+# ---------------------------------------------------------------- block reduce
+@pytest.mark.parametrize("n", [1, 31, 256, 1000, 4096 * 3 + 77, 1 << 20])
+def test_block_reduce(dev, oracle_mod, n):
+    torch, cox = dev
+    say("block_reduce n", n)
+    x = inputs.block_reduce_input(n)
+    bs, wc = cox.warp_reduce_blocks_i32(up(torch, x))
+    obs, owc = oracle_mod.reduce_blocks_i32(x)
+    assert np.array_equal(down(bs), obs) and np.array_equal(down(wc), owc)
+
+
+# ---------------------------------------------------------------- chunked reduce
+@pytest.mark.parametrize("k,W", SIGMAS)
+def test_reduce_i32_and_f32(dev, oracle_mod, k, W):
+    torch, cox = dev
+    n = 3 * 32 * W * k + 123
+    say("reduce sigma", k, W, "n", n)
+    x, _, f = inputs.primitive_inputs(n)
+    t, p = cox.warp_reduce(up(torch, x), cfg=(k, W))
+    op, ot = oracle_mod.reduce(x, k, W)
+    assert np.array_equal(down(p), op) and int(down(t)[0]) == ot
+    t, p = cox.warp_reduce(up(torch, f), cfg=(k, W))
+    op, ot = oracle_mod.reduce(f, k, W)
+    assert np.array_equal(down(p).view(np.uint32), op.view(np.uint32))
+    assert down(t).view(np.uint64)[0] == np.float64(ot).view(np.uint64)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("kind", ["sum", "dot"])
+@pytest.mark.parametrize("acc", [0, 1])
+@pytest.mark.parametrize("k,W", [(1, 2), (8, 8), (16, 8), (32, 4)])
+def test_precision_variants_bit_exact(dev, oracle_mod, dtype, kind, acc, k, W):
+    torch, cox = dev
+    n = 5 * 32 * W * k + 1001
+    n += n % 2
+    say("precision", dtype, kind, acc, k, W, n)
+    arrs = inputs.precision_inputs(n, target=1e6, kind=kind, dtype=dtype)
+    data = arrs[:-1]
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    g = [up(torch, a).view(tdt) if dtype == "bf16" else up(torch, a) for a in data]
+    if kind == "sum":
+        t, p = cox.warp_reduce(g[0], acc=acc, cfg=(k, W))
+        op, ot = oracle_mod.reduce(data[0], k, W, acc)
+    else:
+        t, p = cox.warp_dot(g[0], g[1], acc=acc, cfg=(k, W))
+        op, ot = oracle_mod.dot(data[0], data[1], k, W, acc)
+    assert np.array_equal(down(p).view(np.uint32), op.view(np.uint32))
+    assert down(t).view(np.uint64)[0] == np.float64(ot).view(np.uint64)
+
+
+def test_reduce_empty_and_tiny(dev, oracle_mod):
+    torch, cox = dev
+    for n in (0, 1, 5):
+        x = np.arange(1, n + 1, dtype=np.int32)
+        t, _ = cox.warp_reduce(up(torch, x), partials=False)
+        assert int(down(t)[0]) == n * (n + 1) // 2
+        f = np.arange(1, n + 1, dtype=np.float32)
+        t, _ = cox.warp_reduce(up(torch, f), partials=False)
+        want = oracle_mod.reduce(f, 16, 8)[1]
+        assert down(t).view(np.uint64)[0] == np.float64(want).view(np.uint64)
+
+
+# ---------------------------------------------------------------- scan / compaction
+@pytest.mark.parametrize("k,W", SIGMAS)
+def test_scan(dev, oracle_mod, k, W):
+    torch, cox = dev
+    n = 7 * 32 * W * k + 5
+    say("scan sigma", k, W, "n", n)
+    x, _, _ = inputs.primitive_inputs(n)
+    y = down(cox.warp_scan(up(torch, x), cfg=(k, W)))
+    assert np.array_equal(y, oracle_mod.scan_i32(x, k, W))
+
+
+@pytest.mark.parametrize("k,W", SIGMAS)
+def test_compaction(dev, oracle_mod, k, W):
+    torch, cox = dev
+    n = 7 * 32 * W * k + 5
+    say("compact sigma", k, W, "n", n)
+    x, _, _ = inputs.primitive_inputs(n)
+    out, cnt = cox.ballot_compact(up(torch, x), cfg=(k, W))
+    ref, rc = oracle_mod.compact_i32(x, k, W)
+    c = int(down(cnt)[0])
+    assert c == rc and np.array_equal(down(out)[:c], ref)
+
+
+def test_scan_compaction_edge_sizes_and_reuse(dev, oracle_mod):
+    """Back-to-back calls on one workspace (epoch tags), sizes around the
+    chunk size, empty input, and a many-chunk case with small chunks so the
+    look-back walks more than one 32-entry window."""
+    torch, cox = dev
+    S = 32 * 8 * 16
+    for n in (0, 1, 31, S - 1, S, S + 1, 3 * S, 40 * 32 * 2 + 3):
+        x, _, _ = inputs.primitive_inputs(n)
+        xg = up(torch, x)
+        y = down(cox.warp_scan(xg))
+        assert np.array_equal(y, np.cumsum(x.astype(np.int64)).astype(np.int32)), n
+        out, cnt = cox.ballot_compact(xg)
+        c = int(down(cnt)[0])
+        assert c == int((x > 0).sum()) and np.array_equal(down(out)[:c], x[x > 0]), n
+    x, _, _ = inputs.primitive_inputs(200_000)
+    y = down(cox.warp_scan(up(torch, x), cfg=(1, 1)))  # 6250 chunks of 32
+    assert np.array_equal(y, np.cumsum(x.astype(np.int64)).astype(np.int32))
+    for ws in cox._ws_cache.values():
+        ws.status()
+
+
+def test_scan_of_ones_and_determinism(dev):
+    torch, cox = dev
+    n = 1_000_003
+    ones = torch.ones(n, dtype=torch.int32, device="cuda")
+    y = cox.warp_scan(ones)
+    assert torch.equal(y, torch.arange(1, n + 1, dtype=torch.int32, device="cuda"))
+    x, _, f = inputs.primitive_inputs(n)
+    xg = up(torch, x)
+    a = cox.warp_scan(xg)
+    b = cox.warp_scan(xg)
+    assert torch.equal(a, b)
+    fg = up(torch, f)
+    t1, p1 = cox.warp_reduce(fg)
+    t2, p2 = cox.warp_reduce(fg)
+    assert torch.equal(p1, p2) and torch.equal(t1, t2)
+
+
+# ---------------------------------------------------------------- tile sort
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("n", [32, 32 * 3333, 32 * 3333 + 19])
+def test_tile_sort(dev, oracle_mod, k, n):
+    torch, cox = dev
+    say("sort k", k, "n", n)
+    _, keys, _ = inputs.primitive_inputs(n)
+    got = down(cox.tile_sort(up(torch, keys.view(np.int32)), cfg=(k, 0))).view(np.uint32)
+    assert np.array_equal(got, oracle_mod.tile_sort_u32(keys))
+
+
+def test_tile_sort_adversarial_and_zero_one(dev):
+    torch, cox = dev
+    rng = np.random.default_rng(9)
+    cases = [np.full(32 * 64, 7, np.uint32), np.tile(np.arange(32, dtype=np.uint32)[::-1], 64),
+             np.tile(np.array([0, 0xFFFFFFFF], np.uint32), 32 * 32),
+             np.tile(np.array([0x80000000, 0x7FFFFFFF], np.uint32), 32 * 32),
+             (rng.random(32 * 100000) < 0.5).astype(np.uint32)]
+    for c in cases:
+        for k in (1, 4, 8):
+            got = down(cox.tile_sort(up(torch, c.view(np.int32)), cfg=(k, 0))).view(np.uint32)
+            assert np.array_equal(got, np.sort(c.reshape(-1, 32), axis=1).reshape(-1))
+
+
+# ---------------------------------------------------------------- tile reduce / masked
+@pytest.mark.parametrize("T", [2, 4, 8, 16, 32])
+def test_tile_reduce(dev, oracle_mod, T):
+    torch, cox = dev
+    n = 256 * 8 * 5 + 37
+    x = inputs.masked_input(n)
+    got = down(cox.tile_reduce(up(torch, x), T))
+    assert np.array_equal(got, oracle_mod.tile_reduce_i32(x, T))
+
+
+@pytest.mark.parametrize("D", (0, 1, 102, 512, 922, 1024))
+def test_masked_ops(dev, oracle_mod, D):
+    torch, cox = dev
+    n = 32 * 20011
+    x = inputs.masked_input(n)
+    out, rec = cox.warp_masked(up(torch, x), D)
+    oo, orec = oracle_mod.warp_masked(x, D)
+    assert np.array_equal(down(out), oo)
+    assert np.array_equal(down(rec).view(np.uint32), orec)
