@@ -204,9 +204,16 @@ def warp_reduce_blocks_i32(x, block_sums=None, warp_pos_count=None):
     return block_sums, warp_pos_count
 
 
+def _kw(cfg):
+    if cfg is None:
+        return 0, 0
+    if isinstance(cfg, (tuple, list)):
+        return (tuple(cfg) + (0, 0))[:2]
+    return cfg.items_per_lane, cfg.warps_per_block
+
+
 def _nchunks(n, cfg, op, dt):
-    k, W, _ = cfg if isinstance(cfg, (tuple, list)) else (
-        (cfg.items_per_lane, cfg.warps_per_block, cfg.grid_blocks) if cfg is not None else (0, 0, 0))
+    k, W = _kw(cfg)
     dk, dW, _ = default_cfg(op, dt)
     k, W = k or dk, W or dW
     S = 32 * W * k
