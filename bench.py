@@ -1,0 +1,230 @@
+#!/usr/bin/env python3
+"""Throughput of the warp-primitive hot path on one MI355X.
+
+One step = one pass of the whole primitive set over one batch of 2^28
+synthetic elements already resident in HBM:
+  int32 sum reduce, int32 inclusive scan, ballot compaction (keep x > 0),
+  uint32 32-key bitonic tile sort, FP32 shuffle-tree sum.
+value = elements processed per second over the five kernels (GElem/s).
+
+The JSON line also carries per-kernel GElem/s and HBM fractions, the
+roofline of the dominant kernel (algorithmic bytes over its average launch
+time, timed with HIP events on the stream the kernels run on), and the
+oracle's CPU throughput on a bounded sample of the same inputs.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GElem/s and % of HBM peak per warp-primitive kernel; batched vs per-launch speedup"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def src_hash(paths):
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_SOURCES = {
+    "reduce_i32": ["paper_2112_10034_amd/csrc/reduce.hip", "paper_2112_10034_amd/csrc/cox_warp.hpp"],
+    "scan_i32": ["paper_2112_10034_amd/csrc/scan.hip", "paper_2112_10034_amd/csrc/cox_warp.hpp"],
+    "compact_i32": ["paper_2112_10034_amd/csrc/scan.hip", "paper_2112_10034_amd/csrc/cox_warp.hpp"],
+    "tile_sort_u32": ["paper_2112_10034_amd/csrc/sort.hip", "paper_2112_10034_amd/csrc/cox_warp.hpp"],
+    "reduce_f32": ["paper_2112_10034_amd/csrc/reduce.hip", "paper_2112_10034_amd/csrc/cox_warp.hpp"],
+}
+
+
+def measured_traffic(name, launches_bytes):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; None otherwise."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    k = t.get("kernels", {}).get(name)
+    if not k or k.get("src_hash") != src_hash(KERNEL_SOURCES[name]):
+        return None
+    return k["hbm_bytes_per_launch"]
+
+
+def cpu_baseline(x, keys, f, sample, sig):
+    """The oracle as it stands, on the first `sample` elements of each input."""
+    import oracle
+
+    try:
+        cores = min(16, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        cores = min(16, os.cpu_count() or 1)
+    oracle.set_threads(cores)
+    xs, ks, fs = x[:sample].copy(), keys[:sample].copy(), f[:sample].copy()
+    (kr, Wr), (kS, WS) = sig["reduce"], sig["scan"]
+    t0 = time.perf_counter()
+    oracle.reduce(xs, kr, Wr)
+    oracle.scan_i32(xs, kS, WS)
+    oracle.compact_i32(xs, kS, WS)
+    oracle.tile_sort_u32(ks)
+    oracle.reduce(fs, kr, Wr)
+    dt = time.perf_counter() - t0
+    return {"value": round(5 * sample / dt / 1e9, 4), "unit": "GElem/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {sample} elements of each input, all five primitives once "
+                      f"({dt:.1f} s wall on {cores} threads)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1 << 28, help="elements (default: the full 2^28 workload)")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2112_10034_amd import cox, inputs
+
+    torch.cuda.set_device(0)
+    cox.lib()
+    n = args.n
+    log(f"generating inputs n={n}")
+    x, keys, f = inputs.primitive_inputs(n)
+    xg = torch.from_numpy(x).cuda()
+    kg = torch.from_numpy(keys.view(np.int32)).cuda()
+    fg = torch.from_numpy(f).cuda()
+    y = torch.empty_like(xg)
+    cout = torch.empty_like(xg)
+    cnt = torch.empty(1, dtype=torch.int64, device="cuda")
+    srt = torch.empty_like(kg)
+    ti = torch.empty(1, dtype=torch.int64, device="cuda")
+    tf = torch.empty(1, dtype=torch.float64, device="cuda")
+    sig = {"reduce": cox.default_cfg(cox.OP_REDUCE)[:2], "scan": cox.default_cfg(cox.OP_SCAN)[:2]}
+    sort_k = 4
+    # workspaces and partial buffers are allocated once, outside the timed region
+    kr, Wr = sig["reduce"]
+    nch_r = -(-n // (32 * Wr * kr))
+    pi = torch.empty(nch_r, dtype=torch.int32, device="cuda")
+    pf = torch.empty(nch_r, dtype=torch.float32, device="cuda")
+    cox.workspace(cox.OP_REDUCE, cox.I32, n)
+    cox.workspace(cox.OP_SCAN, cox.I32, n)
+    cox.workspace(cox.OP_COMPACT, cox.I32, n)
+    # one plain device copy of the int32 input (untimed): the reference
+    # kernel for HBM byte counters
+    y.copy_(xg)
+    torch.cuda.synchronize()
+
+    names = ["reduce_i32", "scan_i32", "compact_i32", "tile_sort_u32", "reduce_f32"]
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        cox.warp_reduce(xg, total=ti, partials_out=pi)
+        if ev is not None:
+            ev[1].record()
+        cox.warp_scan(xg, out=y)
+        if ev is not None:
+            ev[2].record()
+        cox.ballot_compact(xg, out=cout, count=cnt)
+        if ev is not None:
+            ev[3].record()
+        cox.tile_sort(kg, cfg=(sort_k, 0), out=srt)
+        if ev is not None:
+            ev[4].record()
+        cox.warp_reduce(fg, total=tf, partials_out=pf)
+        if ev is not None:
+            ev[5].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    start.record()
+    for s in range(args.steps):
+        step(evs[s])
+    end.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    total_ms = start.elapsed_time(end)
+    ms_per_step = total_ms / args.steps
+    per = {nm: sum(evs[s][i].elapsed_time(evs[s][i + 1]) for s in range(args.steps)) / args.steps
+           for i, nm in enumerate(names)}
+    log(f"timed: {ms_per_step:.3f} ms/step (wall {t_wall:.2f} s)")
+
+    kept = int(cnt.item())
+    for ws in cox._ws_cache.values():
+        ws.status()  # raises if a cross-block wait gave up
+    nr = nch_r * 4
+    alg_bytes = {
+        "reduce_i32": 4 * n + nr,
+        "scan_i32": 8 * n,
+        "compact_i32": 4 * n + 4 * kept + 8,
+        "tile_sort_u32": 8 * n,
+        "reduce_f32": 4 * n + nr,
+    }
+    kernels = {}
+    for nm in names:
+        ms = per[nm]
+        gbs = alg_bytes[nm] / (ms * 1e-3) / 1e9
+        kernels[nm] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
+                       "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    dom = max(names, key=lambda k: per[k])
+    achieved = alg_bytes[dom] / (per[dom] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, alg_bytes[dom]),
+            "algorithmic_bytes_per_launch": alg_bytes[dom]}
+
+    out = {
+        "metric": METRIC,
+        "value": round(5 * n / (ms_per_step * 1e-3) / 1e9, 2),
+        "unit": "GElem/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i32+u32+f32",
+        "data": "synthetic (seeded numpy PCG64: int32 U[-2^20, 2^20], uint32 uniform keys, float32 N(0,1))",
+        "config": {"workload": "warp primitive set over 2^28 elements: int32 sum, int32 inclusive scan, "
+                               "ballot compaction (x > 0), uint32 32-key tile sort, fp32 tree sum",
+                   "n": n, "sigma_reduce": list(sig["reduce"]), "sigma_scan": list(sig["scan"]),
+                   "sort_keys_per_lane": sort_k},
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        sample = min(args.cpu_sample, n)
+        log(f"cpu baseline: oracle on {sample} elements")
+        out["cpu_baseline"] = cpu_baseline(x, keys, f, sample, sig)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -236,6 +236,16 @@ cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, 
 cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *out, uint32_t *rec,
                            void *stream);
 
+/* ---------------------------------------------------------------------
+ * Bandwidth reference kernels (not part of the method): a plain read and
+ * a plain copy with 16-byte accesses.  They give the achievable HBM
+ * ceiling and the known-size reference for hardware byte counters.
+ * bytes % 16 == 0; pointers 16-byte aligned; grid_blocks 0 = fill the
+ * device.  cox_stream_read xors every word into *sink (device uint32).
+ * ------------------------------------------------------------------- */
+cox_status cox_stream_read(const void *x, size_t bytes, uint32_t *sink, int32_t grid_blocks, void *stream);
+cox_status cox_stream_copy(const void *src, void *dst, size_t bytes, int32_t grid_blocks, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

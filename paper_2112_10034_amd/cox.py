@@ -60,6 +60,8 @@ _SIGS = {
     "cox_tile_sort": (_I, [_P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
     "cox_tile_reduce": (_I, [_P, _I64, _I, _P, _P]),
     "cox_warp_masked": (_I, [_P, _I64, _I, _P, _P, _P]),
+    "cox_stream_read": (_I, [_P, _SZ, _P, C.c_int32, _P]),
+    "cox_stream_copy": (_I, [_P, _P, _SZ, C.c_int32, _P]),
 }
 
 
@@ -307,3 +309,20 @@ def warp_masked(x, density, out=None, rec=None):
     _check(lib().cox_warp_masked(_ptr(x), n, int(density), _ptr(out), _ptr(rec), _stream()),
            "cox_warp_masked")
     return out, rec
+
+
+def stream_read(x, sink=None, grid_blocks=0):
+    """Bandwidth reference: reads every byte of tensor x once."""
+    sink = torch.zeros(1, dtype=torch.int32, device=x.device) if sink is None else sink
+    _check(lib().cox_stream_read(_ptr(x), x.numel() * x.element_size(), _ptr(sink), int(grid_blocks),
+                                 _stream()), "cox_stream_read")
+    return sink
+
+
+def stream_copy(src, dst, grid_blocks=0):
+    """Bandwidth reference: copies src into dst (same byte size)."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("size mismatch")
+    _check(lib().cox_stream_copy(_ptr(src), _ptr(dst), nb, int(grid_blocks), _stream()), "cox_stream_copy")
+    return dst

@@ -2,6 +2,7 @@
 // warp-function probes (warp builtins applied to arrays).
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <utility>
 
 #include "cox_internal.hpp"
@@ -36,22 +37,22 @@ int device_cus() {
   return cus;
 }
 
-int blocks_per_cu(const void *kernel, int block) {
+int blocks_per_cu(const void *kernel, int block, size_t dyn_lds) {
   static std::mutex mu;
-  static std::map<std::pair<const void *, int>, int> cache;
+  static std::map<std::tuple<const void *, int, size_t>, int> cache;
   std::lock_guard<std::mutex> g(mu);
-  auto key = std::make_pair(kernel, block);
+  auto key = std::make_tuple(kernel, block, dyn_lds);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, 0) != hipSuccess || nb <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, dyn_lds) != hipSuccess || nb <= 0)
     nb = 1;
   cache[key] = nb;
   return nb;
 }
 
-int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested) {
-  int64_t g = requested > 0 ? requested : (int64_t)blocks_per_cu(kernel, block) * device_cus();
+int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested, size_t dyn_lds) {
+  int64_t g = requested > 0 ? requested : (int64_t)blocks_per_cu(kernel, block, dyn_lds) * device_cus();
   if (g > work_items) g = work_items;
   if (g < 1) g = 1;
   return (int)g;
@@ -182,7 +183,7 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
   const int64_t nch = (n + S - 1) / S;
   switch (op) {
   case COX_OP_REDUCE:
-  case COX_OP_DOT:
+  case COX_OP_DOT: return WS_HEADER + 16 * (size_t)(nch + 1);  // up to two tagged words per chunk
   case COX_OP_SCAN:
   case COX_OP_COMPACT: return WS_HEADER + 8 * (size_t)(nch + 1);
   case COX_OP_SEGMENTED: {

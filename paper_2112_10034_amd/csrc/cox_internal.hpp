@@ -66,8 +66,8 @@ __device__ __forceinline__ void st_stream4(void *p, uint32_t a, uint32_t b, uint
 void set_hip_error(hipError_t e);
 cox_status launch_status();                      // hipGetLastError -> status
 int device_cus();                                // compute units of the current device
-int blocks_per_cu(const void *kernel, int block);  // occupancy, cached per (kernel, block)
-int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested);
+int blocks_per_cu(const void *kernel, int block, size_t dyn_lds = 0);  // occupancy, cached
+int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested, size_t dyn_lds = 0);
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 inline bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }

@@ -7,8 +7,14 @@
 //
 // k_reduce: chunked sum / dot under the fixed schedule sigma = (k, W)
 // (documented in cox.h); persistent blocks walk chunks c = b, b + G, ...;
-// every chunk partial is stored, and the last block to finish (device-scope
-// counter) runs the FP64 (or int64) final combine.
+// every chunk partial is published as a 64-bit word [tag | value bits]
+// with a device-scope atomic store (tag = this call's epoch), and the last
+// block to finish (device-scope counter) collects the words, checking each
+// tag, and runs the FP64 (or int64) final combine.  No memory fences are
+// needed: a word with the current tag can only hold this call's partial,
+// and the last block resets the counter and advances the epoch only after
+// it has seen every block's words, whose tags every block derived from its
+// own read of the epoch.
 //
 // The shfl_down tree is evaluated at lane 0, which only ever reads
 // in-range sources (offset o reads lanes below 2o); the exchanges use the
@@ -192,20 +198,57 @@ __device__ __forceinline__ double tree_f64(double v) {
   return v;
 }
 
+// chunk partial: optional plain copy for the caller, tagged word(s) for the
+// final combine (two words per chunk for TWOSUM: s then c)
 template <int DT, int ACC>
-__device__ __forceinline__ void store_partial(void *part, int64_t c, const Acc &a) {
-  if constexpr (DT == DT_I32) ((int32_t *)part)[c] = (int32_t)a.i;
-  else if constexpr (ACC == COX_ACC_PLAIN) ((float *)part)[c] = a.s;
-  else ((float2 *)part)[c] = make_float2(a.s, a.c);
+__device__ __forceinline__ void store_partial(void *part, uint64_t *pw, uint32_t tag, int64_t c, const Acc &a) {
+  const uint64_t hi = (uint64_t)tag << 32;
+  if constexpr (DT == DT_I32) {
+    if (part) ((int32_t *)part)[c] = (int32_t)a.i;
+    st_dev(&pw[c], hi | a.i);
+  } else if constexpr (ACC == COX_ACC_PLAIN) {
+    if (part) ((float *)part)[c] = a.s;
+    st_dev(&pw[c], hi | (uint32_t)f2i(a.s));
+  } else {
+    if (part) ((float2 *)part)[c] = make_float2(a.s, a.c);
+    st_dev(&pw[2 * c], hi | (uint32_t)f2i(a.s));
+    st_dev(&pw[2 * c + 1], hi | (uint32_t)f2i(a.c));
+  }
 }
 
-template <int DT, int ACC>
-__device__ __forceinline__ double partial_f64(const void *part, int64_t c) {
-  if constexpr (ACC == COX_ACC_PLAIN) {
-    return (double)((const float *)part)[c];
-  } else {
-    const float2 q = ((const float2 *)part)[c];
-    return (double)q.x + (double)q.y;
+// a tagged word that did not yet carry `tag` when first read: wait for it
+// (bounded; running out sets HDR_ERR)
+__device__ __noinline__ uint64_t wait_word(const uint64_t *p, uint32_t tag, uint32_t *hdr) {
+  uint64_t s = ld_dev(p);
+  uint32_t spins = 0;
+  while ((uint32_t)(s >> 32) != tag) {
+    if (++spins >= MAX_SPIN) {
+      st_dev32(&hdr[HDR_ERR], tag);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    s = ld_dev(p);
+  }
+  return s;
+}
+
+// value bits of FB tagged words p[i0 + b*stride] (b < FB, index < lim):
+// all loads are issued first, then any word not yet carrying the tag is
+// waited for; out-of-range entries get `pad`
+template <int FB>
+__device__ __forceinline__ void take_words(const uint64_t *p, int64_t i0, int64_t stride, int64_t lim,
+                                           uint32_t tag, uint32_t *hdr, uint32_t pad, uint32_t (&out)[FB]) {
+  uint64_t w[FB];
+#pragma unroll
+  for (int b = 0; b < FB; b++) {
+    const int64_t i = i0 + (int64_t)b * stride;
+    w[b] = i < lim ? ld_dev(&p[i]) : (((uint64_t)tag << 32) | pad);
+  }
+#pragma unroll
+  for (int b = 0; b < FB; b++) {
+    const int64_t i = i0 + (int64_t)b * stride;
+    if ((uint32_t)(w[b] >> 32) != tag) w[b] = wait_word(&p[i], tag, hdr);
+    out[b] = (uint32_t)w[b];
   }
 }
 
@@ -220,31 +263,32 @@ __global__ __launch_bounds__(1024) void k_reduce(const void *__restrict__ x, con
   constexpr uint32_t YPAD = 0u;                                // +0.0f
   __shared__ Acc slot[32];
   __shared__ double fin[256];
-  __shared__ uint32_t s_last;
+  __shared__ uint32_t s_last, s_epoch;
 
   const int W = blockDim.x >> 5;
+  uint64_t *pw = (uint64_t *)(hdr + HDR_WORDS);
+  if (threadIdx.x == 0) s_epoch = ld_dev32(&hdr[HDR_EPOCH]);
+  __syncthreads();
+  const uint32_t epoch = s_epoch;
+  const uint32_t tag = tag_of_epoch(epoch);
   const int w = threadIdx.x >> 5, l = threadIdx.x & 31;
   const int64_t S = (int64_t)blockDim.x * K;
 
-  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+  // Full chunks c = blockIdx.x + i * gridDim.x run double-buffered: the
+  // next chunk's vectors are requested (unconditionally, from a clamped
+  // chunk index) before the current chunk is reduced, so loads stay in
+  // flight across the block's barriers.  The partial last chunk (if any) is
+  // reduced afterwards with element-wise bounds.
+  const int64_t nfull = n / S;
+  auto load_full = [&](int64_t c, uint32_t (&xr)[R][V], uint32_t (&yr)[R][V]) {
     const int64_t wbase = c * S + (int64_t)w * 32 * K;
-    uint32_t xr[R][V], yr[R][V];
-    if ((c + 1) * S <= n) {
 #pragma unroll
-      for (int i = 0; i < R; i++) {
-        load_vec<ESZ, V>(x, wbase + (int64_t)(i * 32 + l) * V, xr[i]);
-        if constexpr (OP == OP_DOT) load_vec<ESZ, V>(y, wbase + (int64_t)(i * 32 + l) * V, yr[i]);
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < R; i++)
-#pragma unroll
-        for (int v = 0; v < V; v++) {
-          const int64_t e = wbase + (int64_t)(i * 32 + l) * V + v;
-          xr[i][v] = e < n ? load_one<ESZ>(x, e) : XPAD;
-          if constexpr (OP == OP_DOT) yr[i][v] = e < n ? load_one<ESZ>(y, e) : YPAD;
-        }
+    for (int i = 0; i < R; i++) {
+      load_vec<ESZ, V>(x, wbase + (int64_t)(i * 32 + l) * V, xr[i]);
+      if constexpr (OP == OP_DOT) load_vec<ESZ, V>(y, wbase + (int64_t)(i * 32 + l) * V, yr[i]);
     }
+  };
+  auto reduce_chunk = [&](int64_t c, const uint32_t (&xr)[R][V], const uint32_t (&yr)[R][V]) {
     Acc a = acc_identity<DT, ACC>();
 #pragma unroll
     for (int i = 0; i < R; i++)
@@ -256,22 +300,58 @@ __global__ __launch_bounds__(1024) void k_reduce(const void *__restrict__ x, con
     if (w == 0) {
       Acc b = l < W ? slot[l] : acc_identity<DT, ACC>();
       b = warp_tree<DT, ACC>(b);
-      if (l == 0) store_partial<DT, ACC>(part, c, b);
+      if (l == 0) store_partial<DT, ACC>(part, pw, tag, c, b);
     }
     __syncthreads();
+  };
+  if (nfull > 0) {
+    uint32_t xa[R][V], ya[R][V], xb[R][V], yb[R][V];
+    int64_t c = blockIdx.x;
+    load_full(c < nfull ? c : nfull - 1, xa, ya);
+    while (c < nfull) {
+      int64_t cn = c + gridDim.x;
+      load_full(cn < nfull ? cn : c, xb, yb);
+      reduce_chunk(c, xa, ya);
+      c = cn;
+      if (c >= nfull) break;
+      cn = c + gridDim.x;
+      load_full(cn < nfull ? cn : c, xa, ya);
+      reduce_chunk(c, xb, yb);
+      c = cn;
+    }
+  }
+  if (nfull * S < n && blockIdx.x == nfull % gridDim.x) {
+    uint32_t xr[R][V], yr[R][V];
+    const int64_t wbase = nfull * S + (int64_t)w * 32 * K;
+#pragma unroll
+    for (int i = 0; i < R; i++)
+#pragma unroll
+      for (int v = 0; v < V; v++) {
+        const int64_t e = wbase + (int64_t)(i * 32 + l) * V + v;
+        xr[i][v] = e < n ? load_one<ESZ>(x, e) : XPAD;
+        yr[i][v] = (OP == OP_DOT && e < n) ? load_one<ESZ>(y, e) : YPAD;
+      }
+    reduce_chunk(nfull, xr, yr);
   }
 
-  // last block to finish combines the chunk partials
-  __threadfence();
-  if (threadIdx.x == 0) s_last = (atomicAdd(&hdr[HDR_DONE], 1u) == gridDim.x - 1) ? 1u : 0u;
+  // the last block to finish combines the chunk partials
+  if (threadIdx.x == 0) s_last = (add_dev32(&hdr[HDR_DONE], 1u) == gridDim.x - 1) ? 1u : 0u;
   __syncthreads();
   if (!s_last) return;
-  __threadfence();
 
+  // Loads of the partials are issued in batches of FB independent loads per
+  // thread before they are added, so the fixed serial order costs one
+  // memory latency per batch rather than one per chunk.
+  constexpr int FB = 32;
   if constexpr (DT == DT_I32) {
     __shared__ long long isum[32];
     long long s = 0;
-    for (int64_t c = threadIdx.x; c < nch; c += blockDim.x) s += (long long)((const int32_t *)part)[c];
+    for (int64_t c0 = threadIdx.x; c0 < nch; c0 += (int64_t)FB * blockDim.x) {
+      uint32_t buf[FB];
+      take_words<FB>(pw, c0, blockDim.x, nch, tag, hdr, 0u, buf);
+#pragma unroll
+      for (int b = 0; b < FB; b++) s += (long long)(int32_t)buf[b];
+    }
     // block sum of int64 (order does not matter for integers)
     for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
     if (l == 0) isum[w] = s;
@@ -280,13 +360,32 @@ __global__ __launch_bounds__(1024) void k_reduce(const void *__restrict__ x, con
       long long tot = 0;
       for (int j = 0; j < W; j++) tot += isum[j];
       *(long long *)total = tot;
-      hdr[HDR_DONE] = 0u;
+      st_dev32(&hdr[HDR_DONE], 0u);
+      st_dev32(&hdr[HDR_EPOCH], epoch + 1u);
     }
   } else {
-    // FP64 final tree shaped like a 256-thread block (see cox.h)
+    // FP64 final tree shaped like a 256-thread block (see cox.h); a chain
+    // padded with -0.0 at its end is unchanged
     for (int j = threadIdx.x; j < 256; j += blockDim.x) {
       double s = -0.0;
-      for (int64_t c = j; c < nch; c += 256) s = s + partial_f64<DT, ACC>(part, c);
+      for (int64_t c0 = j; c0 < nch; c0 += (int64_t)FB * 256) {
+        double buf[FB];
+        if constexpr (ACC == COX_ACC_PLAIN) {
+          uint32_t v[FB];
+          take_words<FB>(pw, c0, 256, nch, tag, hdr, 0x80000000u, v);
+#pragma unroll
+          for (int b = 0; b < FB; b++) buf[b] = (double)i2f((int)v[b]);
+        } else {
+          // words 2c (s) and 2c + 1 (c); padding (-0.0, -0.0) adds -0.0
+          uint32_t vs[FB], vc[FB];
+          take_words<FB>(pw, 2 * c0, 512, 2 * nch, tag, hdr, 0x80000000u, vs);
+          take_words<FB>(pw, 2 * c0 + 1, 512, 2 * nch, tag, hdr, 0x80000000u, vc);
+#pragma unroll
+          for (int b = 0; b < FB; b++) buf[b] = (double)i2f((int)vs[b]) + (double)i2f((int)vc[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < FB; b++) s = s + buf[b];
+      }
       fin[j] = s;
     }
     __syncthreads();
@@ -301,7 +400,8 @@ __global__ __launch_bounds__(1024) void k_reduce(const void *__restrict__ x, con
       top = tree_f64(top);
       if (l == 0) {
         *(double *)total = top;
-        hdr[HDR_DONE] = 0u;
+        st_dev32(&hdr[HDR_DONE], 0u);
+        st_dev32(&hdr[HDR_EPOCH], epoch + 1u);
       }
     }
   }
@@ -355,7 +455,7 @@ static cox_status reduce_any(const void *x, const void *y, cox_dtype dtype, int 
   const int block = 32 * sg.W;
   const int64_t S = (int64_t)block * sg.k;
   const int64_t nch = (n + S - 1) / S;
-  void *part = chunk_partials ? chunk_partials : (void *)((char *)ws + WS_HEADER);
+  void *part = chunk_partials;  // optional plain copy; tagged words live in the workspace
   const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, y, n, nch, part, total,
                      (uint32_t *)ws);

@@ -47,25 +47,35 @@ __device__ __forceinline__ uint32_t warp_sum_u32(uint32_t v) {
   return v;
 }
 
-// Decoupled look-back, run by the 32 lanes of logical warp 0.  Publishes
-// the chunk's aggregate, walks back over predecessor status words 32 at a
-// time, and publishes the inclusive prefix.  Returns the exclusive prefix
-// (same in every lane).
-__device__ uint32_t lookback(int64_t c, uint32_t agg, uint64_t *__restrict__ status, uint32_t tag,
-                             uint32_t *__restrict__ hdr) {
+// Decoupled look-back, run by the 32 lanes of logical warp 0, in two
+// halves so that other loads can be issued in between: lookback_begin
+// publishes the chunk's aggregate and requests the first window of
+// predecessor status words (lane l reads chunk c - 1 - l); lookback_end
+// waits for them, walks further back 32 chunks at a time until a lane
+// finds an inclusive prefix, and publishes the chunk's inclusive prefix.
+// Returns the exclusive prefix (same in every lane).
+__device__ __forceinline__ uint64_t lookback_begin(int64_t c, uint32_t agg, uint64_t *__restrict__ status,
+                                                   uint32_t tag) {
   const int l = llane();
   if (c == 0) {
     if (l == 0) st_dev(&status[0], st_pack(tag, ST_PREFIX, agg));
-    return 0u;
+    return 0;
   }
   if (l == 0) st_dev(&status[c], st_pack(tag, ST_AGG, agg));
+  const int64_t idx = c - 1 - l;
+  return idx >= 0 ? ld_dev(&status[idx]) : st_pack(tag, ST_PREFIX, 0u);
+}
+
+__device__ uint32_t lookback_end(int64_t c, uint32_t agg, uint64_t first, uint64_t *__restrict__ status,
+                                 uint32_t tag, uint32_t *__restrict__ hdr) {
+  const int l = llane();
+  if (c == 0) return 0u;
   uint32_t run = 0u;
   int64_t top = c - 1;
+  uint64_t s = first;
   for (;;) {
     const int64_t idx = top - l;
-    uint32_t flag = ST_PREFIX, val = 0u;
     if (idx >= 0) {
-      uint64_t s = ld_dev(&status[idx]);
       uint32_t spins = 0;
       while (st_tag(s) != tag || st_flag(s) == 0u) {
         if (++spins >= MAX_SPIN || ((spins & 1023u) == 0u && ld_dev32(&hdr[HDR_ERR]) == tag)) {
@@ -75,9 +85,8 @@ __device__ uint32_t lookback(int64_t c, uint32_t agg, uint64_t *__restrict__ sta
         __builtin_amdgcn_s_sleep(1);
         s = ld_dev(&status[idx]);
       }
-      flag = st_flag(s);
-      val = st_val(s);
     }
+    const uint32_t flag = st_flag(s), val = st_val(s);
     const uint32_t pm = ballot(flag == ST_PREFIX);
     if (pm) {
       const int p = __builtin_ctz(pm);
@@ -86,6 +95,7 @@ __device__ uint32_t lookback(int64_t c, uint32_t agg, uint64_t *__restrict__ sta
     }
     run += warp_sum_u32(val);
     top -= 32;
+    s = top - l >= 0 ? ld_dev(&status[top - l]) : st_pack(tag, ST_PREFIX, 0u);
   }
   if (l == 0) st_dev(&status[c], st_pack(tag, ST_PREFIX, agg + run));
   return run;
@@ -99,216 +109,207 @@ __device__ __forceinline__ void finish_call(uint32_t *hdr, uint32_t ticket, uint
   }
 }
 
-template <int K>
-__global__ __launch_bounds__(1024) void k_scan_i32(const int32_t *__restrict__ x, int32_t *__restrict__ y,
-                                                   int64_t n, int64_t nch, uint64_t *__restrict__ status,
-                                                   uint32_t *__restrict__ hdr) {
+enum { MODE_SCAN = 0, MODE_COMPACT = 1 };
+
+// One kernel for both look-back operations.  Per block: draw a ticket,
+// then for every full chunk c: (1) row work on c's registers (scan: lane
+// prefixes, warp scans, warp carry; compaction: ballots, ranks, warp
+// count), (2) draw the next ticket and request its vectors into the other
+// register buffer (a ticket past the full chunks reloads c, which is
+// always valid, so the loads are unconditional), (3) warp 0 scans the warp
+// values and runs the look-back, (4) outputs of c.  The partial last chunk
+// is handled after the loop with element-wise bounds.
+template <int K, int MODE>
+__global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x, int32_t *__restrict__ out,
+                                                   long long *__restrict__ count, int64_t n, int64_t nch,
+                                                   uint64_t *__restrict__ status, uint32_t *__restrict__ hdr) {
   constexpr int V = K < 4 ? K : 4;
   constexpr int R = K / V;
-  __shared__ uint32_t s_epoch, s_ticket;
+  __shared__ uint32_t s_epoch, s_tk[2], s_pre, s_wlast;
   __shared__ uint32_t s_w[32];
+  extern __shared__ int32_t s_stage[];  // compaction: S elements
   const int W = blockDim.x >> 5;
   const int w = threadIdx.x >> 5, l = threadIdx.x & 31;
   const int64_t S = (int64_t)blockDim.x * K;
-  if (threadIdx.x == 0) s_epoch = ld_epoch(hdr);
-
-  for (;;) {
-    if (threadIdx.x == 0) s_ticket = add_dev32(&hdr[HDR_TICKET], 1u);
-    __syncthreads();
-    const int64_t c = s_ticket;
-    if (c >= nch) break;
-    const uint32_t tag = tag_of_epoch(s_epoch);
-    const int64_t wbase = c * S + (int64_t)w * 32 * K;
-    const bool full = (c + 1) * S <= n;
-    uint32_t v[R][V];
-    if (full) {
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
-        if constexpr (V == 4) {
-          const uint4 q = *(const uint4 *)(x + e);
-          v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
-        } else if constexpr (V == 2) {
-          const uint2 q = *(const uint2 *)(x + e);
-          v[i][0] = q.x; v[i][1] = q.y;
-        } else {
-          v[i][0] = (uint32_t)x[e];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < R; i++)
-#pragma unroll
-        for (int j = 0; j < V; j++) {
-          const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-          v[i][j] = e < n ? (uint32_t)x[e] : 0u;
-        }
-    }
-    // rows: lane prefix, warp scan of lane totals, running warp carry
-    uint32_t carry = 0u;
-#pragma unroll
-    for (int i = 0; i < R; i++) {
-#pragma unroll
-      for (int j = 1; j < V; j++) v[i][j] += v[i][j - 1];
-      const uint32_t r = v[i][V - 1];
-      const uint32_t incl = warp_incl_scan_u32(r);
-      const uint32_t add = carry + (incl - r);
-#pragma unroll
-      for (int j = 0; j < V; j++) v[i][j] += add;
-      carry += (uint32_t)bcast31((int)incl);
-    }
-    if (l == 0) s_w[w] = carry;
-    __syncthreads();
-    if (w == 0) {
-      const uint32_t a = l < W ? s_w[l] : 0u;
-      const uint32_t incl = warp_incl_scan_u32(a);
-      const uint32_t agg = (uint32_t)bcast31((int)incl);
-      const uint32_t pre = lookback(c, agg, status, tag, hdr);
-      if (l < W) s_w[l] = pre + (incl - a);
-    }
-    __syncthreads();
-    const uint32_t off = s_w[w];
-    if (full) {
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
-        if constexpr (V == 4) {
-          st_stream4(y + e, v[i][0] + off, v[i][1] + off, v[i][2] + off, v[i][3] + off);
-        } else if constexpr (V == 2) {
-          uint2 q;
-          q.x = v[i][0] + off; q.y = v[i][1] + off;
-          *(uint2 *)(y + e) = q;
-        } else {
-          y[e] = (int32_t)(v[i][0] + off);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < R; i++)
-#pragma unroll
-        for (int j = 0; j < V; j++) {
-          const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-          if (e < n) y[e] = (int32_t)(v[i][j] + off);
-        }
-    }
+  const int64_t nfull = n / S;
+  if (threadIdx.x == 0) {
+    s_epoch = ld_epoch(hdr);
+    s_tk[0] = add_dev32(&hdr[HDR_TICKET], 1u);
   }
-  if (threadIdx.x == 0) finish_call(hdr, s_ticket, (uint32_t)(nch + gridDim.x - 1), s_epoch);
-}
+  __syncthreads();
+  const uint32_t epoch = s_epoch;
+  const uint32_t tag = tag_of_epoch(epoch);
+  const uint32_t lt = lanemask_lt();
 
-template <int K>
-__global__ __launch_bounds__(1024) void k_compact_i32(const int32_t *__restrict__ x, int32_t *__restrict__ out,
-                                                      long long *__restrict__ count, int64_t n, int64_t nch,
-                                                      uint64_t *__restrict__ status, uint32_t *__restrict__ hdr) {
-  constexpr int V = K < 4 ? K : 4;
-  constexpr int R = K / V;
-  __shared__ uint32_t s_epoch, s_ticket;
-  __shared__ uint32_t s_w[32];
-  const int W = blockDim.x >> 5;
-  const int w = threadIdx.x >> 5, l = threadIdx.x & 31;
-  const int64_t S = (int64_t)blockDim.x * K;
-  if (threadIdx.x == 0) s_epoch = ld_epoch(hdr);
-
-  for (;;) {
-    if (threadIdx.x == 0) s_ticket = add_dev32(&hdr[HDR_TICKET], 1u);
-    __syncthreads();
-    const int64_t c = s_ticket;
-    if (c >= nch) break;
-    const uint32_t tag = tag_of_epoch(s_epoch);
+  auto load_full = [&](int64_t c, uint32_t (&v)[R][V]) {
     const int64_t wbase = c * S + (int64_t)w * 32 * K;
-    const bool full = (c + 1) * S <= n;
-    int32_t v[R][V];
-    if (full) {
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
-        if constexpr (V == 4) {
-          const int4 q = *(const int4 *)(x + e);
-          v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
-        } else if constexpr (V == 2) {
-          const int2 q = *(const int2 *)(x + e);
-          v[i][0] = q.x; v[i][1] = q.y;
-        } else {
-          v[i][0] = x[e];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < R; i++)
-#pragma unroll
-        for (int j = 0; j < V; j++) {
-          const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-          v[i][j] = e < n ? x[e] : 0;
-        }
-    }
-    // warp-local ranks from ballots
-    const uint32_t lt = lanemask_lt();
-    uint32_t rank[R][V];
-    uint32_t run = 0u;
 #pragma unroll
     for (int i = 0; i < R; i++) {
-      uint32_t base = 0u, rowcnt = 0u, own = 0u;
-#pragma unroll
-      for (int j = 0; j < V; j++) {
-        const uint32_t B = ballot(v[i][j] > 0);
-        base += __popc(B & lt);
-        rowcnt += __popc(B);
+      const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+      if constexpr (V == 4) {
+        const uint4 q = *(const uint4 *)(x + e);
+        v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
+      } else if constexpr (V == 2) {
+        const uint2 q = *(const uint2 *)(x + e);
+        v[i][0] = q.x; v[i][1] = q.y;
+      } else {
+        v[i][0] = (uint32_t)x[e];
       }
-#pragma unroll
-      for (int j = 0; j < V; j++) {
-        rank[i][j] = run + base + own;
-        own += v[i][j] > 0 ? 1u : 0u;
-      }
-      run += rowcnt;
     }
-    if (l == 0) s_w[w] = run;
-    __syncthreads();
-    if (w == 0) {
-      const uint32_t a = l < W ? s_w[l] : 0u;
-      const uint32_t incl = warp_incl_scan_u32(a);
-      const uint32_t agg = (uint32_t)bcast31((int)incl);
-      const uint32_t pre = lookback(c, agg, status, tag, hdr);
-      if (l < W) s_w[l] = pre + (incl - a);
-      if (c == nch - 1 && l == 0) *count = (long long)pre + (long long)agg;
-    }
-    __syncthreads();
-    const uint32_t off = s_w[w];
+  };
+  auto load_tail = [&](int64_t c, uint32_t (&v)[R][V]) {
+    const int64_t wbase = c * S + (int64_t)w * 32 * K;
 #pragma unroll
     for (int i = 0; i < R; i++)
 #pragma unroll
       for (int j = 0; j < V; j++) {
-        // the bound only matters if a look-back wait gave up (HDR_ERR set)
-        const uint64_t pos = (uint64_t)off + rank[i][j];
-        if (v[i][j] > 0 && pos < (uint64_t)n) out[pos] = v[i][j];
+        const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
+        v[i][j] = e < n ? (uint32_t)x[e] : 0u;
       }
+  };
+
+  // process chunk c held in cur; when `full`, prefetch the next ticket's
+  // chunk into nxt.  Returns the next ticket.
+  auto process = [&](int64_t c, uint32_t (&cur)[R][V], uint32_t (&nxt)[R][V], bool full) -> int64_t {
+    uint32_t aux[R][V];  // compaction: ranks inside the warp
+    uint32_t wval = 0u;  // warp carry (scan) or warp count (compaction)
+    if constexpr (MODE == MODE_SCAN) {
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+#pragma unroll
+        for (int j = 1; j < V; j++) cur[i][j] += cur[i][j - 1];
+        const uint32_t r = cur[i][V - 1];
+        const uint32_t incl = warp_incl_scan_u32(r);
+        const uint32_t add = wval + (incl - r);
+#pragma unroll
+        for (int j = 0; j < V; j++) cur[i][j] += add;
+        wval += (uint32_t)bcast31((int)incl);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        uint32_t base = 0u, rowcnt = 0u, own = 0u;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const uint32_t B = ballot((int32_t)cur[i][j] > 0);
+          base += __popc(B & lt);
+          rowcnt += __popc(B);
+        }
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          aux[i][j] = wval + base + own;
+          own += (int32_t)cur[i][j] > 0 ? 1u : 0u;
+        }
+        wval += rowcnt;
+      }
+    }
+    if (l == 0) s_w[w] = wval;
+    if (l == 0 && w == W - 1) s_wlast = wval;
+    if (threadIdx.x == 0) s_tk[1] = add_dev32(&hdr[HDR_TICKET], 1u);
+    __syncthreads();
+    const int64_t cn = s_tk[1];
+    // warp 0: scan of the warp values, aggregate published, first window
+    // of predecessor words requested -- before this block's prefetch, so
+    // that waiting for the window does not also wait for the prefetch
+    uint32_t wa = 0u, wincl = 0u, agg = 0u;
+    uint64_t first = 0;
+    if (w == 0) {
+      wa = l < W ? s_w[l] : 0u;
+      wincl = warp_incl_scan_u32(wa);
+      agg = (uint32_t)bcast31((int)wincl);
+      first = lookback_begin(c, agg, status, tag);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (full) load_full(cn < nfull ? cn : c, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    if (w == 0) {
+      const uint32_t pre = lookback_end(c, agg, first, status, tag, hdr);
+      if (l < W) s_w[l] = pre + (wincl - wa);
+      if (l == 0) s_pre = pre;
+      if constexpr (MODE == MODE_COMPACT)
+        if (c == nch - 1 && l == 0) *count = (long long)pre + (long long)agg;
+    }
+    __syncthreads();
+    const uint32_t off = s_w[w];
+    const int64_t wbase = c * S + (int64_t)w * 32 * K;
+    if constexpr (MODE == MODE_SCAN) {
+      if (full) {
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+          const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+          if constexpr (V == 4) {
+            st_stream4(out + e, cur[i][0] + off, cur[i][1] + off, cur[i][2] + off, cur[i][3] + off);
+          } else if constexpr (V == 2) {
+            *(uint2 *)(out + e) = make_uint2(cur[i][0] + off, cur[i][1] + off);
+          } else {
+            out[e] = (int32_t)(cur[i][0] + off);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+          for (int j = 0; j < V; j++) {
+            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
+            if (e < n) out[e] = (int32_t)(cur[i][j] + off);
+          }
+      }
+    } else {
+      // kept elements are placed in shared memory at their rank inside the
+      // chunk, then the block writes the chunk's output run with coalesced
+      // stores
+      const uint32_t woff = off - s_pre;  // warp offset inside the chunk
+#pragma unroll
+      for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < V; j++)
+          if ((int32_t)cur[i][j] > 0) s_stage[woff + aux[i][j]] = (int32_t)cur[i][j];
+      __syncthreads();
+      const uint32_t pre = s_pre;
+      const uint32_t cnt = s_w[W - 1] - pre + s_wlast;
+      for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+        // the bound only matters if a look-back wait gave up (HDR_ERR set)
+        const uint64_t pos = (uint64_t)pre + q;
+        if (pos < (uint64_t)n) out[pos] = s_stage[q];
+      }
+      __syncthreads();
+    }
+    return cn;
+  };
+
+  int64_t c = s_tk[0];
+  uint32_t A[R][V], B[R][V];
+  if (c < nfull) {
+    load_full(c, A);
+    for (;;) {
+      c = process(c, A, B, true);
+      if (c >= nfull) break;
+      c = process(c, B, A, true);
+      if (c >= nfull) break;
+    }
+  }
+  if (c < nch) {  // the partial last chunk
+    load_tail(c, A);
+    c = process(c, A, B, false);
   }
   if (threadIdx.x == 0) {
-    if (nch == 0 && s_ticket == (uint32_t)(gridDim.x - 1)) *count = 0;
-    finish_call(hdr, s_ticket, (uint32_t)(nch + gridDim.x - 1), s_epoch);
+    if constexpr (MODE == MODE_COMPACT)
+      if (nch == 0 && c == (int64_t)gridDim.x - 1) *count = 0;
+    finish_call(hdr, (uint32_t)c, (uint32_t)(nch + gridDim.x - 1), epoch);
   }
 }
 
-using scan_fn = void (*)(const int32_t *, int32_t *, int64_t, int64_t, uint64_t *, uint32_t *);
-using compact_fn = void (*)(const int32_t *, int32_t *, long long *, int64_t, int64_t, uint64_t *, uint32_t *);
+using lb_fn = void (*)(const int32_t *, int32_t *, long long *, int64_t, int64_t, uint64_t *, uint32_t *);
 
-static scan_fn pick_scan(int k) {
+template <int MODE>
+static lb_fn pick_lb(int k) {
   switch (k) {
-  case 1: return k_scan_i32<1>;
-  case 2: return k_scan_i32<2>;
-  case 4: return k_scan_i32<4>;
-  case 8: return k_scan_i32<8>;
-  case 16: return k_scan_i32<16>;
-  case 32: return k_scan_i32<32>;
-  }
-  return nullptr;
-}
-static compact_fn pick_compact(int k) {
-  switch (k) {
-  case 1: return k_compact_i32<1>;
-  case 2: return k_compact_i32<2>;
-  case 4: return k_compact_i32<4>;
-  case 8: return k_compact_i32<8>;
-  case 16: return k_compact_i32<16>;
-  case 32: return k_compact_i32<32>;
+  case 1: return k_lookback<1, MODE>;
+  case 2: return k_lookback<2, MODE>;
+  case 4: return k_lookback<4, MODE>;
+  case 8: return k_lookback<8, MODE>;
+  case 16: return k_lookback<16, MODE>;
+  case 32: return k_lookback<32, MODE>;
   }
   return nullptr;
 }
@@ -343,11 +344,11 @@ cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg 
   if (n == 0) return COX_OK;
   if (!y) return COX_ERR_INVALID;
   if (!aligned16(y)) return COX_ERR_ALIGN;
-  scan_fn fn = pick_scan(sg.k);
+  lb_fn fn = pick_lb<MODE_SCAN>(sg.k);
   if (!fn) return COX_ERR_UNSUPPORTED;
   const int block = 32 * sg.W;
   const int grid = persistent_grid((const void *)fn, block, nch, sg.G);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, y, n, nch,
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, y, (long long *)nullptr, n, nch,
                      (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
   return launch_status();
 }
@@ -359,11 +360,13 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
   cox_status st = check_lookback_call(COX_OP_COMPACT, n, x, cfg, ws, ws_bytes, &sg, &nch);
   if (st != COX_OK) return st;
   if (!count || (n > 0 && !out)) return COX_ERR_INVALID;
-  compact_fn fn = pick_compact(sg.k);
+  lb_fn fn = pick_lb<MODE_COMPACT>(sg.k);
   if (!fn) return COX_ERR_UNSUPPORTED;
   const int block = 32 * sg.W;
-  const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, out, (long long *)count, n,
+  const size_t lds = (size_t)block * sg.k * sizeof(int32_t);
+  if (lds > 64 * 1024) return COX_ERR_UNSUPPORTED;
+  const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G, lds);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, (hipStream_t)stream, x, out, (long long *)count, n,
                      nch, (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
   return launch_status();
 }

@@ -92,35 +92,50 @@ __device__ __forceinline__ void store_keys(uint32_t *__restrict__ p, const uint3
   }
 }
 
-// grid-stride over lane vectors; every 32-key group is held by LG lanes of
-// one logical warp (groups never straddle a warp since 32 | 32K).  keys and
-// out may be the same buffer (each lane writes back only the positions it
-// read, after its whole group has been sorted).
+// Grid-stride rounds; in a round a block handles U rows of 256 lane
+// vectors (row u = vectors [base + 256u, base + 256u + 256)), and each
+// thread first requests its U vectors, then sorts and stores them, so U
+// independent loads per lane are in flight.  Every 32-key group is held by
+// LG lanes of one logical warp (groups never straddle a warp since
+// 32 | 32K).  keys and out may be the same buffer (each lane writes back
+// only the positions it read, after its whole group has been sorted).
 template <int K>
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n) {
   constexpr int LG = 32 / K;
+  constexpr int U = K >= 16 ? 1 : 16 / K > 4 ? 4 : 16 / K;
   const int g = (int)(threadIdx.x % LG);
   const int64_t nvec = (n + K - 1) / K;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t per_round = (int64_t)gridDim.x * 256 * U;
   // the whole block iterates together so that partial groups see full warps
-  const int64_t rounds = (nvec + stride - 1) / stride;
+  const int64_t rounds = (nvec + per_round - 1) / per_round;
   for (int64_t it = 0; it < rounds; it++) {
-    const int64_t vi = it * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t e0 = vi * K;
-    uint32_t key[K];
-    if (e0 + K <= n) {
-      load_keys<K>(keys + e0, key);
+    const int64_t vbase = it * per_round + (int64_t)blockIdx.x * 256 * U + threadIdx.x;
+    uint32_t key[U][K];
+    const bool full = (vbase - threadIdx.x + 256 * U) * K <= n;
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < U; u++) load_keys<K>(keys + (vbase + 256 * u) * K, key[u]);
     } else {
 #pragma unroll
-      for (int r = 0; r < K; r++) key[r] = e0 + r < n ? keys[e0 + r] : 0xffffffffu;
+      for (int u = 0; u < U; u++) {
+        const int64_t e0 = (vbase + 256 * u) * K;
+#pragma unroll
+        for (int r = 0; r < K; r++) key[u][r] = e0 + r < n ? keys[e0 + r] : 0xffffffffu;
+      }
     }
-    merge_stages<K, 2>(key, g);
-    if (e0 + K <= n) {
-      store_keys<K>(out + e0, key);
+#pragma unroll
+    for (int u = 0; u < U; u++) merge_stages<K, 2>(key[u], g);
+    if (full) {
+#pragma unroll
+      for (int u = 0; u < U; u++) store_keys<K>(out + (vbase + 256 * u) * K, key[u]);
     } else {
 #pragma unroll
-      for (int r = 0; r < K; r++)
-        if (e0 + r < n) out[e0 + r] = key[r];
+      for (int u = 0; u < U; u++) {
+        const int64_t e0 = (vbase + 256 * u) * K;
+#pragma unroll
+        for (int r = 0; r < K; r++)
+          if (e0 + r < n) out[e0 + r] = key[u][r];
+      }
     }
   }
 }
@@ -152,7 +167,9 @@ extern "C" cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t
   if (!keys || !out) return COX_ERR_INVALID;
   if (!aligned16(keys) || !aligned16(out)) return COX_ERR_ALIGN;
   const int64_t nvec = (n + k - 1) / k;
-  const int grid = persistent_grid((const void *)fn, 256, (nvec + 255) / 256, cfg ? cfg->grid_blocks : 0);
+  const int U = k >= 16 ? 1 : 16 / k > 4 ? 4 : 16 / k;
+  const int grid = persistent_grid((const void *)fn, 256, (nvec + 256 * U - 1) / (256 * U),
+                                   cfg ? cfg->grid_blocks : 0);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, out, n);
   return launch_status();
 }
