@@ -73,17 +73,18 @@ def cpu_baseline(x, keys, f, sample, sig):
         cores = min(16, os.cpu_count() or 1)
     oracle.set_threads(cores)
     xs, ks, fs = x[:sample].copy(), keys[:sample].copy(), f[:sample].copy()
-    (kr, Wr), (kS, WS) = sig["reduce"], sig["scan"]
+    (kr, Wr), (kS, WS), (kC, WC) = sig["reduce"], sig["scan"], sig["compact"]
     t0 = time.perf_counter()
     oracle.reduce(xs, kr, Wr)
     oracle.scan_i32(xs, kS, WS)
-    oracle.compact_i32(xs, kS, WS)
+    oracle.compact_i32(xs, kC, WC)
     oracle.tile_sort_u32(ks)
     oracle.reduce(fs, kr, Wr)
     dt = time.perf_counter() - t0
     return {"value": round(5 * sample / dt / 1e9, 4), "unit": "GElem/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {sample} elements of each input, all five primitives once "
-                      f"({dt:.1f} s wall on {cores} threads)"}
+            "sample": (f"the whole batch ({sample} elements of each input)" if sample == len(x) else
+                       f"first {sample} elements of each input") +
+                      f", all five primitives once ({dt:.1f} s wall on {cores} threads)"}
 
 
 def main():
@@ -92,7 +93,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1 << 28, help="elements (default: the full 2^28 workload)")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 28,
+                    help="elements of each input the oracle runs on (default: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -119,7 +121,8 @@ def main():
     srt = torch.empty_like(kg)
     ti = torch.empty(1, dtype=torch.int64, device="cuda")
     tf = torch.empty(1, dtype=torch.float64, device="cuda")
-    sig = {"reduce": cox.default_cfg(cox.OP_REDUCE)[:2], "scan": cox.default_cfg(cox.OP_SCAN)[:2]}
+    sig = {"reduce": cox.default_cfg(cox.OP_REDUCE)[:2], "scan": cox.default_cfg(cox.OP_SCAN)[:2],
+           "compact": cox.default_cfg(cox.OP_COMPACT)[:2]}
     sort_k = 4
     # workspaces and partial buffers are allocated once, outside the timed region
     kr, Wr = sig["reduce"]
@@ -129,9 +132,9 @@ def main():
     cox.workspace(cox.OP_REDUCE, cox.I32, n)
     cox.workspace(cox.OP_SCAN, cox.I32, n)
     cox.workspace(cox.OP_COMPACT, cox.I32, n)
-    # one plain device copy of the int32 input (untimed): the reference
-    # kernel for HBM byte counters
-    y.copy_(xg)
+    # one plain copy of the int32 input (untimed; 1 GiB read + 1 GiB write):
+    # the known-size reference kernel for HBM byte counters
+    cox.stream_copy(xg, y)
     torch.cuda.synchronize()
 
     names = ["reduce_i32", "scan_i32", "compact_i32", "tile_sort_u32", "reduce_f32"]
@@ -175,6 +178,22 @@ def main():
            for i, nm in enumerate(names)}
     log(f"timed: {ms_per_step:.3f} ms/step (wall {t_wall:.2f} s)")
 
+    # bandwidth references (untimed by the step clock): plain read, plain copy
+    def ref_time(fn, reps=5):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    t_rd = ref_time(lambda: cox.stream_read(xg, sink))
+    t_cp = ref_time(lambda: cox.stream_copy(xg, y))
+    reference = {"stream_read_gb_s": round(4 * n / (t_rd * 1e-3) / 1e9, 1),
+                 "stream_copy_gb_s": round(8 * n / (t_cp * 1e-3) / 1e9, 1)}
+
     kept = int(cnt.item())
     for ws in cox._ws_cache.values():
         ws.status()  # raises if a cross-block wait gave up
@@ -215,9 +234,11 @@ def main():
         "config": {"workload": "warp primitive set over 2^28 elements: int32 sum, int32 inclusive scan, "
                                "ballot compaction (x > 0), uint32 32-key tile sort, fp32 tree sum",
                    "n": n, "sigma_reduce": list(sig["reduce"]), "sigma_scan": list(sig["scan"]),
+                   "sigma_compact": list(sig["compact"]),
                    "sort_keys_per_lane": sort_k},
         "kernels": kernels,
         "roofline": roof,
+        "reference": reference,
     }
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, n)

@@ -37,6 +37,21 @@ int device_cus() {
   return cus;
 }
 
+size_t device_max_lds() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+    v = 65536;
+  cache[dev] = (size_t)v;
+  return (size_t)v;
+}
+
 int blocks_per_cu(const void *kernel, int block, size_t dyn_lds) {
   static std::mutex mu;
   static std::map<std::tuple<const void *, int, size_t>, int> cache;
@@ -51,8 +66,11 @@ int blocks_per_cu(const void *kernel, int block, size_t dyn_lds) {
   return nb;
 }
 
-int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested, size_t dyn_lds) {
-  int64_t g = requested > 0 ? requested : (int64_t)blocks_per_cu(kernel, block, dyn_lds) * device_cus();
+int persistent_grid(const void *kernel, int block, int64_t work_items, int32_t requested, size_t dyn_lds,
+                    int per_cu) {
+  int occ = blocks_per_cu(kernel, block, dyn_lds);
+  if (per_cu < occ) occ = per_cu;
+  int64_t g = requested > 0 ? requested : (int64_t)occ * device_cus();
   if (g > work_items) g = work_items;
   if (g < 1) g = 1;
   return (int)g;
@@ -155,16 +173,20 @@ cox_status cox_default_cfg(cox_op op, cox_dtype dtype, cox_cfg *out) {
   if (!out) return COX_ERR_INVALID;
   out->grid_blocks = 0;
   out->reserved = 0;
+  // measured on MI355X at 2^28 elements (schedule sweep)
   switch (op) {
   case COX_OP_REDUCE:
   case COX_OP_DOT:
     out->items_per_lane = 16;
-    out->warps_per_block = 8;
+    out->warps_per_block = 16;
     break;
   case COX_OP_SCAN:
+    out->items_per_lane = 32;
+    out->warps_per_block = 32;
+    break;
   case COX_OP_COMPACT:
-    out->items_per_lane = 16;
-    out->warps_per_block = 8;
+    out->items_per_lane = 32;
+    out->warps_per_block = 32;
     break;
   case COX_OP_SEGMENTED:
     out->items_per_lane = 8;

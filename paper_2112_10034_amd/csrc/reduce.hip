@@ -72,15 +72,15 @@ __device__ __forceinline__ void load_vec(const void *__restrict__ base, int64_t 
   const char *p = (const char *)base + idx * ESZ;
   uint32_t w[(BYTES + 3) / 4];
   if constexpr (BYTES == 16) {
-    uint4 q = *(const uint4 *)p;
+    const u32x4 q = ld_stream4(p);
     w[0] = q.x; w[1] = q.y; w[2] = q.z; w[3] = q.w;
   } else if constexpr (BYTES == 8) {
-    uint2 q = *(const uint2 *)p;
+    const u32x2 q = ld_stream2(p);
     w[0] = q.x; w[1] = q.y;
   } else if constexpr (BYTES == 4) {
-    w[0] = *(const uint32_t *)p;
+    w[0] = ld_stream1(p);
   } else {
-    w[0] = *(const uint16_t *)p;
+    w[0] = ld_stream_h(p);
   }
   if constexpr (ESZ == 4) {
 #pragma unroll
@@ -93,8 +93,8 @@ __device__ __forceinline__ void load_vec(const void *__restrict__ base, int64_t 
 
 template <int ESZ>
 __device__ __forceinline__ uint32_t load_one(const void *__restrict__ base, int64_t idx) {
-  if constexpr (ESZ == 4) return ((const uint32_t *)base)[idx];
-  else return (uint32_t)((const uint16_t *)base)[idx] << 16;
+  if constexpr (ESZ == 4) return ld_stream1((const uint32_t *)base + idx);
+  else return (uint32_t)ld_stream_h((const uint16_t *)base + idx) << 16;
 }
 
 // per-lane accumulator
@@ -436,6 +436,11 @@ static reduce_fn pick(int dt, int op, int acc, int k) {
   return nullptr;
 }
 
+// default persistent grid: about 512 threads per compute unit (measured
+// best for streaming reads on MI355X: fewer concurrent streams keep DRAM
+// pages open)
+static int reduce_blocks_per_cu(int block) { return block >= 512 ? 1 : 512 / block; }
+
 static cox_status reduce_any(const void *x, const void *y, cox_dtype dtype, int op, int64_t n, cox_acc acc,
                              const cox_cfg *cfg, void *chunk_partials, void *total, void *ws,
                              size_t ws_bytes, void *stream) {
@@ -456,7 +461,7 @@ static cox_status reduce_any(const void *x, const void *y, cox_dtype dtype, int 
   const int64_t S = (int64_t)block * sg.k;
   const int64_t nch = (n + S - 1) / S;
   void *part = chunk_partials;  // optional plain copy; tagged words live in the workspace
-  const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G);
+  const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G, 0, reduce_blocks_per_cu(block));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, y, n, nch, part, total,
                      (uint32_t *)ws);
   return launch_status();

@@ -15,8 +15,10 @@
 //
 // Compaction: p = (x > 0); per row and vector slot v a ballot B_v; the
 // rank of (l, v) inside the row is sum_v' popc(B_v' & lanemask_lt) plus the
-// lane's own earlier slots; warp counts are scanned in shared memory and
-// chunk offsets chained by the same look-back.
+// lane's own earlier slots.  Kept elements are staged in the warp's own
+// shared-memory region at their rank, warp counts are scanned in shared
+// memory, chunk offsets chained by the same look-back, and each warp then
+// writes its run with coalesced stores.
 //
 // Chunks are claimed from a ticket counter, so a chunk only ever waits for
 // chunks that running blocks already hold.  Every block finally draws one
@@ -125,9 +127,9 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
                                                    uint64_t *__restrict__ status, uint32_t *__restrict__ hdr) {
   constexpr int V = K < 4 ? K : 4;
   constexpr int R = K / V;
-  __shared__ uint32_t s_epoch, s_tk[2], s_pre, s_wlast;
+  __shared__ uint32_t s_epoch, s_tk[2];
   __shared__ uint32_t s_w[32];
-  extern __shared__ int32_t s_stage[];  // compaction: S elements
+  extern __shared__ int32_t s_stage[];  // compaction: 32K elements per warp
   const int W = blockDim.x >> 5;
   const int w = threadIdx.x >> 5, l = threadIdx.x & 31;
   const int64_t S = (int64_t)blockDim.x * K;
@@ -141,19 +143,24 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
   const uint32_t tag = tag_of_epoch(epoch);
   const uint32_t lt = lanemask_lt();
 
-  auto load_full = [&](int64_t c, uint32_t (&v)[R][V]) {
-    const int64_t wbase = c * S + (int64_t)w * 32 * K;
+  // vectors of chunk c; with dummy set every lane reads the array's first
+  // vector instead (a ticket past the full chunks: keeps the loads
+  // unconditional while fetching a single line)
+  auto load_full = [&](int64_t c, uint32_t (&v)[R][V], bool dummy) {
+    // one base pointer and one row stride per lane (not a select per load)
+    const int32_t *src = x + (dummy ? 0 : c * S + (int64_t)w * 32 * K + l * V);
+    const int rstride = dummy ? 0 : 32 * V;
 #pragma unroll
     for (int i = 0; i < R; i++) {
-      const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+      const int32_t *p = src + i * rstride;
       if constexpr (V == 4) {
-        const uint4 q = *(const uint4 *)(x + e);
+        const u32x4 q = ld_stream4(p);
         v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
       } else if constexpr (V == 2) {
-        const uint2 q = *(const uint2 *)(x + e);
+        const u32x2 q = ld_stream2(p);
         v[i][0] = q.x; v[i][1] = q.y;
       } else {
-        v[i][0] = (uint32_t)x[e];
+        v[i][0] = ld_stream1(p);
       }
     }
   };
@@ -164,14 +171,13 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
 #pragma unroll
       for (int j = 0; j < V; j++) {
         const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-        v[i][j] = e < n ? (uint32_t)x[e] : 0u;
+        v[i][j] = e < n ? ld_stream1(x + e) : 0u;
       }
   };
 
   // process chunk c held in cur; when `full`, prefetch the next ticket's
   // chunk into nxt.  Returns the next ticket.
   auto process = [&](int64_t c, uint32_t (&cur)[R][V], uint32_t (&nxt)[R][V], bool full) -> int64_t {
-    uint32_t aux[R][V];  // compaction: ranks inside the warp
     uint32_t wval = 0u;  // warp carry (scan) or warp count (compaction)
     if constexpr (MODE == MODE_SCAN) {
 #pragma unroll
@@ -186,6 +192,10 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
         wval += (uint32_t)bcast31((int)incl);
       }
     } else {
+      // ranks inside the warp from ballots; kept elements go to the warp's
+      // own shared-memory region at their rank (written and later read by
+      // the same warp, so no block barrier is needed for it)
+      int32_t *region = s_stage + w * 32 * K;
 #pragma unroll
       for (int i = 0; i < R; i++) {
         uint32_t base = 0u, rowcnt = 0u, own = 0u;
@@ -197,14 +207,13 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
         }
 #pragma unroll
         for (int j = 0; j < V; j++) {
-          aux[i][j] = wval + base + own;
+          if ((int32_t)cur[i][j] > 0) region[wval + base + own] = (int32_t)cur[i][j];
           own += (int32_t)cur[i][j] > 0 ? 1u : 0u;
         }
         wval += rowcnt;
       }
     }
     if (l == 0) s_w[w] = wval;
-    if (l == 0 && w == W - 1) s_wlast = wval;
     if (threadIdx.x == 0) s_tk[1] = add_dev32(&hdr[HDR_TICKET], 1u);
     __syncthreads();
     const int64_t cn = s_tk[1];
@@ -220,12 +229,11 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
       first = lookback_begin(c, agg, status, tag);
     }
     __builtin_amdgcn_sched_barrier(0);
-    if (full) load_full(cn < nfull ? cn : c, nxt);
+    if (full) load_full(cn, nxt, cn >= nfull);
     __builtin_amdgcn_sched_barrier(0);
     if (w == 0) {
       const uint32_t pre = lookback_end(c, agg, first, status, tag, hdr);
       if (l < W) s_w[l] = pre + (wincl - wa);
-      if (l == 0) s_pre = pre;
       if constexpr (MODE == MODE_COMPACT)
         if (c == nch - 1 && l == 0) *count = (long long)pre + (long long)agg;
     }
@@ -240,9 +248,9 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
           if constexpr (V == 4) {
             st_stream4(out + e, cur[i][0] + off, cur[i][1] + off, cur[i][2] + off, cur[i][3] + off);
           } else if constexpr (V == 2) {
-            *(uint2 *)(out + e) = make_uint2(cur[i][0] + off, cur[i][1] + off);
+            st_stream2(out + e, cur[i][0] + off, cur[i][1] + off);
           } else {
-            out[e] = (int32_t)(cur[i][0] + off);
+            st_stream1(out + e, cur[i][0] + off);
           }
         }
       } else {
@@ -255,24 +263,13 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
           }
       }
     } else {
-      // kept elements are placed in shared memory at their rank inside the
-      // chunk, then the block writes the chunk's output run with coalesced
-      // stores
-      const uint32_t woff = off - s_pre;  // warp offset inside the chunk
-#pragma unroll
-      for (int i = 0; i < R; i++)
-#pragma unroll
-        for (int j = 0; j < V; j++)
-          if ((int32_t)cur[i][j] > 0) s_stage[woff + aux[i][j]] = (int32_t)cur[i][j];
-      __syncthreads();
-      const uint32_t pre = s_pre;
-      const uint32_t cnt = s_w[W - 1] - pre + s_wlast;
-      for (uint32_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+      // the warp writes its kept run [off, off + wval) from its region
+      const int32_t *region = s_stage + w * 32 * K;
+      for (uint32_t q = l; q < wval; q += 32) {
         // the bound only matters if a look-back wait gave up (HDR_ERR set)
-        const uint64_t pos = (uint64_t)pre + q;
-        if (pos < (uint64_t)n) out[pos] = s_stage[q];
+        const uint64_t pos = (uint64_t)off + q;
+        if (pos < (uint64_t)n) st_stream1(out + pos, (uint32_t)region[q]);
       }
-      __syncthreads();
     }
     return cn;
   };
@@ -280,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
   int64_t c = s_tk[0];
   uint32_t A[R][V], B[R][V];
   if (c < nfull) {
-    load_full(c, A);
+    load_full(c, A, false);
     for (;;) {
       c = process(c, A, B, true);
       if (c >= nfull) break;
@@ -363,10 +360,13 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
   lb_fn fn = pick_lb<MODE_COMPACT>(sg.k);
   if (!fn) return COX_ERR_UNSUPPORTED;
   const int block = 32 * sg.W;
-  const size_t lds = (size_t)block * sg.k * sizeof(int32_t);
-  if (lds > 64 * 1024) return COX_ERR_UNSUPPORTED;
+  const size_t lds = (size_t)block * sg.k * sizeof(int32_t) + 256;  // staging + static
+  if (lds > device_max_lds()) return COX_ERR_UNSUPPORTED;
+  if (lds - 256 > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(lds - 256)) != hipSuccess)
+    return COX_ERR_UNSUPPORTED;
   const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G, lds);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, (hipStream_t)stream, x, out, (long long *)count, n,
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds - 256, (hipStream_t)stream, x, out, (long long *)count, n,
                      nch, (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
   return launch_status();
 }

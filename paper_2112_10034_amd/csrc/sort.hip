@@ -68,14 +68,14 @@ __device__ __forceinline__ void load_keys(const uint32_t *__restrict__ p, uint32
   if constexpr (K % 4 == 0) {
 #pragma unroll
     for (int q = 0; q < K / 4; q++) {
-      const uint4 v = ((const uint4 *)p)[q];
+      const u32x4 v = ld_stream4(p + 4 * q);
       key[4 * q] = v.x; key[4 * q + 1] = v.y; key[4 * q + 2] = v.z; key[4 * q + 3] = v.w;
     }
   } else if constexpr (K == 2) {
-    const uint2 v = *(const uint2 *)p;
+    const u32x2 v = ld_stream2(p);
     key[0] = v.x; key[1] = v.y;
   } else {
-    key[0] = *p;
+    key[0] = ld_stream1(p);
   }
 }
 
@@ -86,9 +86,9 @@ __device__ __forceinline__ void store_keys(uint32_t *__restrict__ p, const uint3
     for (int q = 0; q < K / 4; q++)
       st_stream4(p + 4 * q, key[4 * q], key[4 * q + 1], key[4 * q + 2], key[4 * q + 3]);
   } else if constexpr (K == 2) {
-    *(uint2 *)p = make_uint2(key[0], key[1]);
+    st_stream2(p, key[0], key[1]);
   } else {
-    *p = key[0];
+    st_stream1(p, key[0]);
   }
 }
 
@@ -168,8 +168,9 @@ extern "C" cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t
   if (!aligned16(keys) || !aligned16(out)) return COX_ERR_ALIGN;
   const int64_t nvec = (n + k - 1) / k;
   const int U = k >= 16 ? 1 : 16 / k > 4 ? 4 : 16 / k;
+  // default: two 256-thread blocks per compute unit (measured best)
   const int grid = persistent_grid((const void *)fn, 256, (nvec + 256 * U - 1) / (256 * U),
-                                   cfg ? cfg->grid_blocks : 0);
+                                   cfg ? cfg->grid_blocks : 0, 0, 2);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, out, n);
   return launch_status();
 }

@@ -2,9 +2,10 @@
 //
 // Both kernels keep CUDA's one-element-per-lane mapping: element e sits in
 // logical lane e & 31 of logical warp e >> 5.  A block handles R rows of 256
-// consecutive elements per round (coalesced 4-byte loads, R loads in
-// flight per thread), and the whole block runs every round so that the
-// fixed-pattern exchanges always see full warps.
+// consecutive elements per round (coalesced streaming 4-byte loads, R loads
+// in flight per thread), and the whole block runs every round so that the
+// fixed-pattern exchanges always see full warps.  The default grid is four
+// 256-thread blocks per compute unit.
 #include "cox_internal.hpp"
 
 namespace cox {
@@ -34,7 +35,7 @@ __global__ __launch_bounds__(256) void k_tile_reduce(const int32_t *__restrict__
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int64_t e = base + r * 256 + t;
-      v[r] = e < n ? (uint32_t)x[e] : 0u;
+      v[r] = e < n ? ld_stream1(x + e) : 0u;
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__
 #pragma unroll
     for (int r = 0; r < R; r++) {
       const int64_t e = base + r * 256 + t;
-      xs[r] = e < n ? x[e] : 0;
+      xs[r] = e < n ? (int32_t)ld_stream1(x + e) : 0;
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -113,7 +114,7 @@ cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, 
   if (!fn) return COX_ERR_INVALID;
   if (n == 0) return COX_OK;
   if (!x || !out) return COX_ERR_INVALID;
-  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 8 - 1) / (256 * 8), 0);
+  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 8 - 1) / (256 * 8), 0, 0, 4);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, x, n, out);
   return launch_status();
 }
@@ -125,7 +126,7 @@ cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *ou
   if (!x || !out || !rec) return COX_ERR_INVALID;
   if (!aligned16(rec)) return COX_ERR_ALIGN;
   auto fn = k_warp_masked<8>;
-  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 8 - 1) / (256 * 8), 0);
+  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 8 - 1) / (256 * 8), 0, 0, 4);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, x, n, density, out, rec);
   return launch_status();
 }
