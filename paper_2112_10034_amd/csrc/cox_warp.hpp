@@ -120,16 +120,31 @@ __device__ __forceinline__ int swz(int v) {
   return __builtin_amdgcn_ds_swizzle(v, (XOR << 10) | (OR << 5) | AND);
 }
 
+// DPP move for patterns whose every source lane is valid (no "old" value
+// needed, so no copy into the destination first)
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
+}
+
 // value of logical partner lane l ^ M (M < 32), fixed pattern
 template <int M>
 __device__ __forceinline__ int xor_lane(int v) {
-  if constexpr (M == 1) return dpp<DPP_QUAD_XOR1>(v, v);
-  else if constexpr (M == 2) return dpp<DPP_QUAD_XOR2>(v, v);
-  else if constexpr (M == 3) return dpp<DPP_QUAD_XOR3>(v, v);
-  else if constexpr (M == 7) return dpp<DPP_ROW_HALF_MIRROR>(v, v);
-  else if constexpr (M == 8) return dpp<DPP_ROW_ROR8>(v, v);
-  else if constexpr (M == 15) return dpp<DPP_ROW_MIRROR>(v, v);
+  if constexpr (M == 1) return dpp_mov<DPP_QUAD_XOR1>(v);
+  else if constexpr (M == 2) return dpp_mov<DPP_QUAD_XOR2>(v);
+  else if constexpr (M == 3) return dpp_mov<DPP_QUAD_XOR3>(v);
+  else if constexpr (M == 7) return dpp_mov<DPP_ROW_HALF_MIRROR>(v);
+  else if constexpr (M == 8) return dpp_mov<DPP_ROW_ROR8>(v);
+  else if constexpr (M == 15) return dpp_mov<DPP_ROW_MIRROR>(v);
   else return swz<0x1f, 0, M>(v);
+}
+
+// median of three unsigned values (one v_med3_u32); med3(a, b, 0) is
+// min(a, b) and med3(a, b, ~0) is max(a, b)
+__device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
 }
 
 // logical lane 31's value in every lane of the half

@@ -268,7 +268,9 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
       for (uint32_t q = l; q < wval; q += 32) {
         // the bound only matters if a look-back wait gave up (HDR_ERR set)
         const uint64_t pos = (uint64_t)off + q;
-        if (pos < (uint64_t)n) st_stream1(out + pos, (uint32_t)region[q]);
+        // plain stores: the warp's 4-byte stores of one run are merged into
+        // whole lines in L2 (streaming stores would reach HBM as partial lines)
+        if (pos < (uint64_t)n) out[pos] = region[q];
       }
     }
     return cn;

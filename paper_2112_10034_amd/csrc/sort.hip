@@ -33,16 +33,14 @@ __device__ __forceinline__ void cx_layer(uint32_t (&key)[K], int g) {
       }
     }
   } else {
+    // the lower lane of a pair keeps min = med3(a, b, 0), the upper one
+    // max = med3(a, b, ~0): one exchange and one median per key
     uint32_t other[K];
 #pragma unroll
     for (int r = 0; r < K; r++) other[r] = (uint32_t)xor_lane<LM>((int)key[r ^ RM]);
-    const bool lower = (g & (LB / K)) == 0;
+    const uint32_t sel = (g & (LB / K)) ? 0xffffffffu : 0u;
 #pragma unroll
-    for (int r = 0; r < K; r++) {
-      const uint32_t mn = key[r] < other[r] ? key[r] : other[r];
-      const uint32_t mx = key[r] < other[r] ? other[r] : key[r];
-      key[r] = lower ? mn : mx;
-    }
+    for (int r = 0; r < K; r++) key[r] = med3u(key[r], other[r], sel);
   }
 }
 
