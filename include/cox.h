@@ -237,6 +237,76 @@ cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *ou
                            void *stream);
 
 /* ---------------------------------------------------------------------
+ * Segmented batching: thousands of uneven CSR segments in one persistent
+ * launch.  The paper runs one CUDA block per CPU thread through pthread
+ * fork/join per kernel launch (Sec. 4) and names a reusable thread pool
+ * as the better runtime; here every chunk of every segment is a ticket of
+ * one queue drained by a persistent grid, and a plan captures the whole
+ * call (setup kernels + fused kernel) in a hipGraph.
+ *
+ * Segment s = x[offsets[s], offsets[s+1]) (offsets: device int64[nseg+1],
+ * non-decreasing, within [0, n]; x: device int32 or float32 [n], 16-byte
+ * aligned).  Offsets cannot be checked before launch; the kernels clamp
+ * every segment to [0, n] (a reversed segment is empty), so bad offsets
+ * give meaningless results but no access outside x.  Chunks of S = 32 * warps_per_block * items_per_lane
+ * elements start at each segment's first element (items_per_lane <= 16).
+ *   seg_total[s] : device int64 (int32 input) = sum of the int32-wrapped
+ *                  chunk partials as int64; device double (float input) =
+ *                  FP64 sum, from -0.0 in chunk order, of the chunk
+ *                  partials (each the sigma reduce tree of cox_cfg);
+ *   y            : inclusive scan restarting at every segment, at the
+ *                  positions of x; int32 wraps; float: chunk-local scan
+ *                  q by the documented shuffle tree, then
+ *                  (float)(C_j + (double)q) with C_j the FP64 sum from
+ *                  -0.0 in chunk order of the earlier chunks' totals;
+ *   out_compact  : the elements > 0 of segment s, in order, written at
+ *                  out_compact[offsets[s] ...]; seg_count[s] (device
+ *                  int64) their number.
+ * An empty segment gets total 0 / -0.0 and count 0.  `which` selects the
+ * outputs: 1 = totals, 2 = scan, 4 = compaction (or any sum).  Workspace:
+ * cox_workspace_bytes(COX_OP_SEGMENTED, dtype, n, nseg, cfg).
+ * ------------------------------------------------------------------- */
+cox_status cox_segmented(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                         void *seg_total, void *y, void *out_compact, int64_t *seg_count, int which,
+                         const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
+cox_status cox_segmented_reduce(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                                void *seg_total, const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
+cox_status cox_segmented_scan(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                              void *y, const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
+cox_status cox_segmented_compact(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                                 void *out_compact, int64_t *seg_count, const cox_cfg *cfg, void *ws,
+                                 size_t ws_bytes, void *stream);
+/* all three outputs in one fused launch (which = 7) */
+cox_status cox_segmented_fused(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                               void *seg_total, void *y, void *out_compact, int64_t *seg_count, const cox_cfg *cfg,
+                               void *ws, size_t ws_bytes, void *stream);
+/* The per-segment baseline: the same fused kernel launched once per
+ * segment (offsets_host: host copy of offsets, used for grid sizes). */
+cox_status cox_segmented_per_segment(const void *x, cox_dtype dtype, const int64_t *offsets,
+                                     const int64_t *offsets_host, int64_t nseg, int64_t n, void *seg_total, void *y,
+                                     void *out_compact, int64_t *seg_count, const cox_cfg *cfg, void *ws,
+                                     size_t ws_bytes, void *stream);
+
+/* A plan: one segmented call bound to its buffers and captured in a
+ * hipGraph on a stream of the plan's own.  With autotune != 0 and no
+ * schedule given (cfg NULL or items/warps zero), creation first runs the
+ * call for a set of candidate (items_per_lane, warps_per_block, grid)
+ * and keeps the fastest; the chosen schedule (which fixes the float
+ * results) is reported by cox_plan_get_cfg.  Creation runs the call
+ * (outputs are overwritten) and synchronises; ws must be large enough for
+ * every candidate tried (candidates that do not fit are skipped).
+ * cox_plan_execute replays the graph on `stream`; a plan must not run
+ * concurrently with itself or with another call on the same workspace. */
+typedef struct cox_plan_s *cox_plan;
+cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                              void *seg_total, void *y, void *out_compact, int64_t *seg_count, int which,
+                              const cox_cfg *cfg, int autotune, void *ws, size_t ws_bytes, void *stream,
+                              cox_plan *plan);
+cox_status cox_plan_execute(cox_plan plan, void *stream);
+cox_status cox_plan_get_cfg(cox_plan plan, cox_cfg *cfg);
+cox_status cox_plan_destroy(cox_plan plan);
+
+/* ---------------------------------------------------------------------
  * Bandwidth reference kernels (not part of the method): a plain read and
  * a plain copy with 16-byte accesses.  They give the achievable HBM
  * ceiling and the known-size reference for hardware byte counters.

@@ -60,6 +60,18 @@ _SIGS = {
     "cox_tile_sort": (_I, [_P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
     "cox_tile_reduce": (_I, [_P, _I64, _I, _P, _P]),
     "cox_warp_masked": (_I, [_P, _I64, _I, _P, _P, _P]),
+    "cox_segmented": (_I, [_P, _I, _P, _I64, _I64, _P, _P, _P, _P, _I, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_segmented_reduce": (_I, [_P, _I, _P, _I64, _I64, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_segmented_scan": (_I, [_P, _I, _P, _I64, _I64, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_segmented_compact": (_I, [_P, _I, _P, _I64, _I64, _P, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_segmented_fused": (_I, [_P, _I, _P, _I64, _I64, _P, _P, _P, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_segmented_per_segment": (_I, [_P, _I, _P, _P, _I64, _I64, _P, _P, _P, _P, C.POINTER(cox_cfg), _P,
+                                       _SZ, _P]),
+    "cox_plan_segmented": (_I, [_P, _I, _P, _I64, _I64, _P, _P, _P, _P, _I, C.POINTER(cox_cfg), _I, _P, _SZ, _P,
+                                C.POINTER(C.c_void_p)]),
+    "cox_plan_execute": (_I, [_P, _P]),
+    "cox_plan_get_cfg": (_I, [_P, C.POINTER(cox_cfg)]),
+    "cox_plan_destroy": (_I, [_P]),
     "cox_stream_read": (_I, [_P, _SZ, _P, C.c_int32, _P]),
     "cox_stream_copy": (_I, [_P, _P, _SZ, C.c_int32, _P]),
 }
@@ -326,3 +338,97 @@ def stream_copy(src, dst, grid_blocks=0):
         raise ValueError("size mismatch")
     _check(lib().cox_stream_copy(_ptr(src), _ptr(dst), nb, int(grid_blocks), _stream()), "cox_stream_copy")
     return dst
+
+
+# ---------------------------------------------------------------- segmented
+SEG_REDUCE, SEG_SCAN, SEG_COMPACT = 1, 2, 4
+
+# the plan autotuner's candidates all use chunks of at least 1024 elements
+_SEG_MIN_CHUNK_CFG = (4, 8)
+
+
+def _seg_outputs(x, offsets, which, seg_total, y, out, seg_count):
+    dt = _dtype_code(x)
+    nseg = offsets.numel() - 1
+    dev = x.device
+    if which & SEG_REDUCE and seg_total is None:
+        seg_total = torch.empty(nseg, dtype=torch.int64 if dt == I32 else torch.float64, device=dev)
+    if which & SEG_SCAN and y is None:
+        y = torch.empty_like(x)
+    if which & SEG_COMPACT:
+        if out is None:
+            out = torch.zeros_like(x)
+        if seg_count is None:
+            seg_count = torch.empty(nseg, dtype=torch.int64, device=dev)
+    return dt, nseg, seg_total, y, out, seg_count
+
+
+def segmented(x, offsets, which=7, cfg=None, seg_total=None, y=None, out=None, seg_count=None):
+    """Segmented totals / scan / compaction over CSR offsets (device int64,
+    nseg + 1 entries) in one fused launch.  Returns (seg_total, y, out,
+    seg_count) with None for outputs not selected by `which`."""
+    _need(offsets, torch.int64, "offsets")
+    if x.dtype not in (torch.int32, torch.float32):
+        raise TypeError("x must be int32 or float32")
+    _need(x, x.dtype, "x")
+    dt, nseg, seg_total, y, out, seg_count = _seg_outputs(x, offsets, which, seg_total, y, out, seg_count)
+    ws = workspace(OP_SEGMENTED, dt, x.numel(), nseg, cfg=cfg, device=x.device)
+    _check(lib().cox_segmented(_ptr(x), dt, _ptr(offsets), nseg, x.numel(), _ptr(seg_total), _ptr(y), _ptr(out),
+                               _ptr(seg_count), int(which), _cfgp(cfg), _ptr(ws.tensor), ws.nbytes, _stream()),
+           "cox_segmented")
+    return seg_total, y, out, seg_count
+
+
+def segmented_per_segment(x, offsets, offsets_host, cfg=None, seg_total=None, y=None, out=None, seg_count=None):
+    """Baseline: the fused kernel launched once per segment."""
+    _need(offsets, torch.int64, "offsets")
+    _need(x, x.dtype, "x")
+    oh = offsets_host.contiguous()
+    dt, nseg, seg_total, y, out, seg_count = _seg_outputs(x, offsets, 7, seg_total, y, out, seg_count)
+    ws = workspace(OP_SEGMENTED, dt, x.numel(), nseg, cfg=cfg, device=x.device)
+    _check(lib().cox_segmented_per_segment(_ptr(x), dt, _ptr(offsets), C.c_void_p(oh.data_ptr()), nseg, x.numel(),
+                                           _ptr(seg_total), _ptr(y), _ptr(out), _ptr(seg_count), _cfgp(cfg),
+                                           _ptr(ws.tensor), ws.nbytes, _stream()), "cox_segmented_per_segment")
+    return seg_total, y, out, seg_count
+
+
+class Plan:
+    """A segmented call bound to its buffers and captured in a hipGraph;
+    execute() replays it on torch's current stream."""
+
+    def __init__(self, x, offsets, which=7, cfg=None, autotune=True, seg_total=None, y=None, out=None,
+                 seg_count=None):
+        _need(offsets, torch.int64, "offsets")
+        _need(x, x.dtype, "x")
+        dt, nseg, self.seg_total, self.y, self.out, self.seg_count = _seg_outputs(
+            x, offsets, which, seg_total, y, out, seg_count)
+        self.x, self.offsets = x, offsets
+        wcfg = cfg if cfg is not None and any(_kw(cfg)) else _SEG_MIN_CHUNK_CFG
+        nbytes = lib().cox_workspace_bytes(OP_SEGMENTED, dt, x.numel(), nseg, _cfgp(wcfg))
+        self.ws = Workspace(nbytes, x.device)  # a plan owns its workspace
+        h = C.c_void_p()
+        _check(lib().cox_plan_segmented(_ptr(x), dt, _ptr(offsets), nseg, x.numel(), _ptr(self.seg_total),
+                                        _ptr(self.y), _ptr(self.out), _ptr(self.seg_count), int(which), _cfgp(cfg),
+                                        int(bool(autotune)), _ptr(self.ws.tensor), self.ws.nbytes, _stream(),
+                                        C.byref(h)), "cox_plan_segmented")
+        self.handle = h
+
+    def execute(self):
+        _check(lib().cox_plan_execute(self.handle, _stream()), "cox_plan_execute")
+        return self.seg_total, self.y, self.out, self.seg_count
+
+    def cfg(self):
+        c = cox_cfg()
+        _check(lib().cox_plan_get_cfg(self.handle, C.byref(c)), "cox_plan_get_cfg")
+        return (c.items_per_lane, c.warps_per_block, c.grid_blocks)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().cox_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

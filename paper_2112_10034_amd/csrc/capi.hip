@@ -189,7 +189,7 @@ cox_status cox_default_cfg(cox_op op, cox_dtype dtype, cox_cfg *out) {
     out->warps_per_block = 32;
     break;
   case COX_OP_SEGMENTED:
-    out->items_per_lane = 8;
+    out->items_per_lane = 4;
     out->warps_per_block = 8;
     break;
   default: return COX_ERR_INVALID;
@@ -209,11 +209,12 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
   case COX_OP_SCAN:
   case COX_OP_COMPACT: return WS_HEADER + 8 * (size_t)(nch + 1);
   case COX_OP_SEGMENTED: {
-    // chunks of every segment (each segment rounds up) + per-segment and
-    // per-chunk words; nseg < 0 is invalid
+    // chunks of every segment (each segment rounds up): chunk starts and
+    // done counters per segment, a map word and four status words per chunk
     if (nseg < 0) return 0;
-    const int64_t maxch = nch + nseg;
-    return WS_HEADER + 8 * (size_t)(nseg + 2) + 32 * (size_t)(maxch + 1);
+    const int64_t maxch = n / S + nseg + 1;
+    return WS_HEADER + 4 * (size_t)(nseg + 1) + 8 + 4 * (size_t)nseg + 8 + 4 * (size_t)maxch + 8 +
+           32 * (size_t)maxch;
   }
   }
   return 0;

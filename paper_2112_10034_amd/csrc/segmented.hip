@@ -1,0 +1,898 @@
+// Segmented reduce + scan + compaction over CSR segments, fused in one
+// persistent launch.
+//
+// Segment s covers x[off[s], off[s+1]).  It is cut into chunks of
+// S = 32 * W * k elements starting at its first element (the last chunk is
+// padded), and every chunk of every segment becomes one ticket of a single
+// queue, so thousands of uneven segments share one grid.  A setup pass (one
+// block) turns the segment lengths into per-segment chunk starts, a second
+// one writes the chunk -> segment map, and empty segments get their
+// identity outputs there.
+//
+// Per chunk (element layout of the schedule sigma = (k, W), cox.h):
+//  - reduce partial P: lane-serial accumulation in (row, slot) order, the
+//    shfl_down tree per warp, the same tree over the warp values;
+//  - chunk-local inclusive scan q: lane-serial prefix over the row's
+//    slots; per row a Kogge-Stone shfl_up(d, 16) for d = 1, 2, 4, 8, then
+//    lane 15's value added into lanes 16-31 (DPP row_shr / row_bcast:15),
+//    the lane-exclusive value shfl_up(r, 1) and the row total from lane 31;
+//    warp carry over rows; warp 0 scans the warp totals with the same
+//    tree; q = ((E_w + C_i) + ex_l) + z_v, absent terms being the identity;
+//  - ballot compaction (x > 0) with ranks from ballots, staged in the
+//    warp's own LDS region.
+// Across the chunks of a segment:
+//  - int32 scan carry and compaction offsets: decoupled look-back bounded
+//    below by the segment's first chunk;
+//  - float scan carry C_j: the FP64 sum, in chunk order from -0.0, of the
+//    earlier chunks' totals T (q at the chunk's last slot), each chunk
+//    reading the published totals of its predecessors; output
+//    (float)(C_j + (double)q);
+//  - totals: every chunk publishes P and counts itself in the segment's
+//    done counter; the chunk completing the count adds the segment's
+//    partials (int64 sum, or FP64 serial ascending from -0.0).
+// All cross-block words carry the call's epoch tag (see scan.hip), waits
+// are bounded, and every counter is reset by its last user, so the launch
+// needs no workspace clearing and can be replayed from a graph.
+#include <stdlib.h>
+
+#include <vector>
+
+#include "cox_internal.hpp"
+
+namespace cox {
+
+enum : int { SHDR_NC = 4 };  // header word: total chunk count (setup pass)
+
+struct SegWS {
+  uint32_t *hdr;
+  uint32_t *chunk_start;  // nseg + 1
+  uint32_t *done;         // nseg
+  int32_t *seg_of_chunk;  // maxch
+  uint64_t *w_scan;       // maxch: look-back words of int chunk sums
+  uint64_t *w_cnt;        // maxch: look-back words of kept counts
+  uint64_t *w_part;       // maxch: [tag | bits] reduce partials
+  uint64_t *w_tot;        // maxch: [tag | bits] float chunk scan totals
+};
+
+static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
+
+// workspace layout for nseg segments and at most maxch chunks
+static SegWS seg_layout(void *ws, int64_t nseg, int64_t maxch, size_t *bytes) {
+  SegWS w;
+  char *p = (char *)ws;
+  size_t o = WS_HEADER;
+  w.hdr = (uint32_t *)p;
+  w.chunk_start = (uint32_t *)(p + o);
+  o = align8(o + 4 * (size_t)(nseg + 1));
+  w.done = (uint32_t *)(p + o);
+  o = align8(o + 4 * (size_t)nseg);
+  w.seg_of_chunk = (int32_t *)(p + o);
+  o = align8(o + 4 * (size_t)maxch);
+  w.w_scan = (uint64_t *)(p + o);
+  o += 8 * (size_t)maxch;
+  w.w_cnt = (uint64_t *)(p + o);
+  o += 8 * (size_t)maxch;
+  w.w_part = (uint64_t *)(p + o);
+  o += 8 * (size_t)maxch;
+  w.w_tot = (uint64_t *)(p + o);
+  o += 8 * (size_t)maxch;
+  if (bytes) *bytes = o;
+  return w;
+}
+
+enum : int { SF_REDUCE = 1, SF_SCAN = 2, SF_COMPACT = 4 };
+
+// segment bounds clamped to [0, n] (offsets live on the device and cannot
+// be checked before launch; a bad segment becomes empty or shorter instead
+// of reaching outside x)
+__device__ __forceinline__ void seg_bounds(const int64_t *off, int64_t s, int64_t n, int64_t &a, int64_t &b) {
+  a = off[s];
+  b = off[s + 1];
+  a = a < 0 ? 0 : (a > n ? n : a);
+  b = b < a ? a : (b > n ? n : b);
+}
+
+// ---------------------------------------------------------------- setup
+// One block of 1024 threads: chunk counts ceil(len / S) scanned into
+// per-segment chunk starts (32-bit), the total written to hdr[SHDR_NC];
+// empty segments get total = identity and count = 0.
+template <int DT>
+__global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
+                                                    int64_t S, SegWS ws, void *seg_total, long long *seg_count) {
+  __shared__ uint32_t s_w[32];
+  __shared__ uint32_t s_carry;
+  const int t = threadIdx.x, w = t >> 5, l = t & 31;
+  if (t == 0) s_carry = 0u;
+  __syncthreads();
+  for (int64_t base = 0; base < nseg; base += 1024) {
+    const int64_t s = base + t;
+    uint32_t cnt = 0u;
+    if (s < nseg) {
+      int64_t a, b;
+      seg_bounds(off, s, n, a, b);
+      const int64_t len = b - a;
+      cnt = (uint32_t)((len + S - 1) / S);
+      if (len == 0) {
+        if (seg_total) {
+          if (DT == COX_I32) ((long long *)seg_total)[s] = 0;
+          else ((double *)seg_total)[s] = -0.0;
+        }
+        if (seg_count) seg_count[s] = 0;
+      }
+    }
+    uint32_t v = cnt;
+    v += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)v);
+    v += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)v);
+    v += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)v);
+    v += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)v);
+    v += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)v);
+    if (l == 31) s_w[w] = v;
+    __syncthreads();
+    if (w == 0) {
+      uint32_t a = s_w[l];
+      uint32_t b = a;
+      b += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)b);
+      b += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)b);
+      b += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)b);
+      b += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)b);
+      b += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)b);
+      s_w[l] = b - a;  // exclusive over warps
+    }
+    __syncthreads();
+    const uint32_t carry = s_carry;
+    const uint32_t excl = carry + s_w[w] + (v - cnt);
+    if (s < nseg) ws.chunk_start[s] = excl;
+    __syncthreads();
+    if (t == 1023) s_carry = excl + cnt;
+    __syncthreads();
+  }
+  if (t == 0) {
+    ws.chunk_start[nseg] = s_carry;
+    ws.hdr[SHDR_NC] = s_carry;
+  }
+}
+
+// one logical warp per segment: chunk -> segment map
+__global__ __launch_bounds__(256) void k_seg_map(int64_t nseg, SegWS ws) {
+  const int64_t wg = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
+  const int64_t nw = ((int64_t)gridDim.x * 256) >> 5;
+  const int l = threadIdx.x & 31;
+  for (int64_t s = wg; s < nseg; s += nw) {
+    const uint32_t a = ws.chunk_start[s], b = ws.chunk_start[s + 1];
+    for (uint32_t c = a + l; c < b; c += 32) ws.seg_of_chunk[c] = (int32_t)s;
+  }
+}
+
+// ---------------------------------------------------------------- element ops
+template <int DT> struct SegT;
+template <> struct SegT<COX_I32> {
+  static constexpr uint32_t ident = 0u;
+  static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
+  static __device__ __forceinline__ bool keep(uint32_t a) { return (int32_t)a > 0; }
+};
+template <> struct SegT<COX_F32> {
+  static constexpr uint32_t ident = 0x80000000u;  // -0.0f
+  static __device__ __forceinline__ uint32_t add(uint32_t a, uint32_t b) {
+    return (uint32_t)f2i(i2f((int)a) + i2f((int)b));
+  }
+  static __device__ __forceinline__ bool keep(uint32_t a) { return i2f((int)a) > 0.0f; }
+};
+
+// shfl_down tree (lane 0's value), own operand first
+template <int DT>
+__device__ __forceinline__ uint32_t seg_tree(uint32_t a) {
+  a = SegT<DT>::add(a, (uint32_t)xor_lane<16>((int)a));
+  a = SegT<DT>::add(a, (uint32_t)xor_lane<8>((int)a));
+  a = SegT<DT>::add(a, (uint32_t)xor_lane<4>((int)a));
+  a = SegT<DT>::add(a, (uint32_t)xor_lane<2>((int)a));
+  a = SegT<DT>::add(a, (uint32_t)xor_lane<1>((int)a));
+  return a;
+}
+
+// the scan tree: r becomes the inclusive value, ex the lane-exclusive one
+// (identity at logical lane 0), returns the 32-lane total
+template <int DT>
+__device__ __forceinline__ uint32_t seg_scan32(uint32_t &r, uint32_t &ex) {
+  constexpr int I = (int)SegT<DT>::ident;
+  r = SegT<DT>::add(r, (uint32_t)dpp<DPP_ROW_SHR1>(I, (int)r));
+  r = SegT<DT>::add(r, (uint32_t)dpp<DPP_ROW_SHR2>(I, (int)r));
+  r = SegT<DT>::add(r, (uint32_t)dpp<DPP_ROW_SHR4>(I, (int)r));
+  r = SegT<DT>::add(r, (uint32_t)dpp<DPP_ROW_SHR8>(I, (int)r));
+  r = SegT<DT>::add(r, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(I, (int)r));
+  const uint32_t up = (uint32_t)shfl_up((int)r, 1);
+  ex = llane() == 0 ? SegT<DT>::ident : up;
+  return (uint32_t)bcast31((int)r);
+}
+
+// segment-bounded decoupled look-back (warp 0): chunks below `lo` count as
+// an inclusive prefix of 0
+__device__ uint32_t seg_lookback(int64_t c, int64_t lo, uint32_t agg, uint64_t *__restrict__ st, uint32_t tag,
+                                 uint32_t *__restrict__ hdr) {
+  const int l = llane();
+  if (c == lo) {
+    if (l == 0) st_dev(&st[c], st_pack(tag, ST_PREFIX, agg));
+    return 0u;
+  }
+  if (l == 0) st_dev(&st[c], st_pack(tag, ST_AGG, agg));
+  uint32_t run = 0u;
+  int64_t top = c - 1;
+  for (;;) {
+    const int64_t idx = top - l;
+    uint64_t s = st_pack(tag, ST_PREFIX, 0u);
+    if (idx >= lo) {
+      s = ld_dev(&st[idx]);
+      uint32_t spins = 0;
+      while (st_tag(s) != tag || st_flag(s) == 0u) {
+        if (++spins >= MAX_SPIN || ((spins & 1023u) == 0u && ld_dev32(&hdr[HDR_ERR]) == tag)) {
+          st_dev32(&hdr[HDR_ERR], tag);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        s = ld_dev(&st[idx]);
+      }
+    }
+    const uint32_t pm = ballot(st_flag(s) == ST_PREFIX);
+    uint32_t v = st_val(s);
+    if (pm) {
+      const int p = __builtin_ctz(pm);
+      v = l <= p ? v : 0u;
+      v += (uint32_t)xor_lane<16>((int)v);
+      v += (uint32_t)xor_lane<8>((int)v);
+      v += (uint32_t)xor_lane<4>((int)v);
+      v += (uint32_t)xor_lane<2>((int)v);
+      v += (uint32_t)xor_lane<1>((int)v);
+      run += v;
+      break;
+    }
+    v += (uint32_t)xor_lane<16>((int)v);
+    v += (uint32_t)xor_lane<8>((int)v);
+    v += (uint32_t)xor_lane<4>((int)v);
+    v += (uint32_t)xor_lane<2>((int)v);
+    v += (uint32_t)xor_lane<1>((int)v);
+    run += v;
+    top -= 32;
+  }
+  if (l == 0) st_dev(&st[c], st_pack(tag, ST_PREFIX, agg + run));
+  return run;
+}
+
+// value bits of tagged word p[i] for i in [a, b) (lanes of warp 0 fetch 32
+// at a time); `fold` is applied in index order by lane 0's loop
+__device__ __forceinline__ uint64_t seg_word(const uint64_t *p, int64_t i, uint32_t tag, uint32_t *hdr) {
+  uint64_t s = ld_dev(&p[i]);
+  uint32_t spins = 0;
+  while ((uint32_t)(s >> 32) != tag) {
+    if (++spins >= MAX_SPIN || ((spins & 1023u) == 0u && ld_dev32(&hdr[HDR_ERR]) == tag)) {
+      st_dev32(&hdr[HDR_ERR], tag);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+    s = ld_dev(&p[i]);
+  }
+  return s;
+}
+
+// FP64 serial sum from -0.0 of the float bits in words [a, b), in index
+// order (warp 0; same value in every lane)
+__device__ double seg_serial_f64(const uint64_t *p, int64_t a, int64_t b, uint32_t tag, uint32_t *hdr) {
+  const int l = llane();
+  double acc = -0.0;
+  for (int64_t base = a; base < b; base += 32) {
+    const int64_t i = base + l;
+    float v = -0.0f;
+    if (i < b) v = i2f((int)(uint32_t)seg_word(p, i, tag, hdr));
+    const int m = (int)(b - base < 32 ? b - base : 32);
+    for (int j = 0; j < m; j++) acc = acc + (double)__shfl(v, j, 32);
+  }
+  return acc;
+}
+
+// int64 sum of the int32 bits in words [a, b) (warp 0)
+__device__ long long seg_sum_i64(const uint64_t *p, int64_t a, int64_t b, uint32_t tag, uint32_t *hdr) {
+  const int l = llane();
+  long long acc = 0;
+  for (int64_t i = a + l; i < b; i += 32) acc += (long long)(int32_t)(uint32_t)seg_word(p, i, tag, hdr);
+  for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+  return acc;
+}
+
+// ---------------------------------------------------------------- fused kernel
+template <int K, int DT>
+__global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__ x, const int64_t *__restrict__ off,
+                                                    int64_t nseg, int64_t n, int64_t nc_arg, SegWS ws,
+                                                    void *seg_total, uint32_t *y, uint32_t *outc,
+                                                    long long *seg_count, int flags) {
+  constexpr int V = K < 4 ? K : 4;
+  constexpr int R = K / V;
+  using T = SegT<DT>;
+  __shared__ uint32_t s_epoch, s_ticket, s_seg, s_nchs;
+  __shared__ int64_t s_e0, s_e1, s_lo, s_obase;
+  __shared__ uint32_t s_wred[32], s_wscan[32], s_wcnt[32], s_E[32], s_coff[32];
+  __shared__ uint32_t s_last[3];
+  __shared__ uint32_t s_pre_i, s_pre_c;
+  __shared__ double s_pre_f;
+  extern __shared__ uint32_t s_stage[];  // 32K values per warp (compaction)
+
+  const int W = blockDim.x >> 5;
+  const int w = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int64_t S = (int64_t)blockDim.x * K;
+  const uint32_t lt = lanemask_lt();
+  if (threadIdx.x == 0) s_epoch = ld_epoch(ws.hdr);
+  __syncthreads();
+  const uint32_t epoch = s_epoch;
+  const uint32_t tag = tag_of_epoch(epoch);
+  const int64_t NC = nc_arg >= 0 ? nc_arg : (int64_t)ld_dev32(&ws.hdr[SHDR_NC]);
+
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint32_t t = add_dev32(&ws.hdr[HDR_TICKET], 1u);
+      s_ticket = t;
+      if ((int64_t)t < NC) {
+        const int64_t s = nc_arg >= 0 ? 0 : ws.seg_of_chunk[t];
+        const int64_t lo = nc_arg >= 0 ? 0 : ws.chunk_start[s];
+        const int64_t nchs = nc_arg >= 0 ? nc_arg : (int64_t)ws.chunk_start[s + 1] - lo;
+        int64_t a, b;
+        seg_bounds(off, s, n, a, b);
+        s_seg = (uint32_t)s;
+        s_lo = lo;
+        s_nchs = (uint32_t)nchs;
+        s_obase = a;
+        s_e0 = a + ((int64_t)t - lo) * S;
+        s_e1 = b;
+      }
+    }
+    __syncthreads();
+    const int64_t c = s_ticket;
+    if (c >= NC) break;
+    const int64_t s = s_seg, lo = s_lo, e0 = s_e0, e1 = s_e1;
+    const uint32_t nchs = s_nchs;
+
+    // ---- load (padding with the identity)
+    uint32_t xr[R][V];
+    const int64_t wbase = e0 + (int64_t)w * 32 * K;
+    if (e0 + S <= e1 && V == 4 && (e0 & 3) == 0) {
+      // 16-byte aligned chunk: one vector per row
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+        const u32x4 q = ld_stream4(x + e);
+        xr[i][0] = q[0];
+#pragma unroll
+        for (int j = 1; j < V; j++) xr[i][j] = q[j];
+      }
+    } else if (e0 + S <= e1) {
+      // segments start anywhere: element loads
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+#pragma unroll
+        for (int j = 0; j < V; j++) xr[i][j] = ld_stream1(x + e + j);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
+          xr[i][j] = e < e1 ? ld_stream1(x + e) : T::ident;
+        }
+    }
+
+    // ---- reduce partial: lane-serial then the warp tree
+    if (flags & SF_REDUCE) {
+      uint32_t a = T::ident;
+#pragma unroll
+      for (int i = 0; i < R; i++)
+#pragma unroll
+        for (int j = 0; j < V; j++) a = T::add(a, xr[i][j]);
+      a = seg_tree<DT>(a);
+      if (l == 0) s_wred[w] = a;
+    }
+    // ---- chunk-local scan
+    uint32_t z[R][V], exv[R], cin[R];
+    if (flags & SF_SCAN) {
+      uint32_t carry = T::ident;
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        z[i][0] = xr[i][0];
+#pragma unroll
+        for (int j = 1; j < V; j++) z[i][j] = T::add(z[i][j - 1], xr[i][j]);
+        uint32_t r = z[i][V - 1];
+        const uint32_t rt = seg_scan32<DT>(r, exv[i]);
+        cin[i] = carry;
+        carry = T::add(carry, rt);
+      }
+      if (l == 0) s_wscan[w] = carry;
+      if (w == W - 1 && l == 31) {
+        s_last[0] = cin[R - 1];
+        s_last[1] = exv[R - 1];
+        s_last[2] = z[R - 1][V - 1];
+      }
+    }
+    // ---- compaction ranks, staged in the warp's LDS region
+    if (flags & SF_COMPACT) {
+      uint32_t *region = s_stage + w * 32 * K;
+      uint32_t run = 0u;
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        uint32_t base = 0u, rowcnt = 0u, own = 0u;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const uint32_t B = ballot(T::keep(xr[i][j]));
+          base += __popc(B & lt);
+          rowcnt += __popc(B);
+        }
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const bool k = T::keep(xr[i][j]);
+          if (k) region[run + base + own] = xr[i][j];
+          own += k ? 1u : 0u;
+        }
+        run += rowcnt;
+      }
+      if (l == 0) s_wcnt[w] = run;
+    }
+    __syncthreads();
+
+    // ---- warp 0: block combines, publication, look-backs, totals
+    if (w == 0) {
+      uint32_t agg_s = 0u, agg_c = 0u;
+      if (flags & SF_REDUCE) {
+        uint32_t b = l < W ? s_wred[l] : T::ident;
+        b = seg_tree<DT>(b);
+        if (l == 0) st_dev(&ws.w_part[c], ((uint64_t)tag << 32) | b);
+      }
+      if (flags & SF_SCAN) {
+        uint32_t a = l < W ? s_wscan[l] : T::ident;
+        uint32_t ex;
+        const uint32_t tot = seg_scan32<DT>(a, ex);
+        s_E[l] = ex;  // lanes >= W are not read
+        if constexpr (DT == COX_I32) {
+          agg_s = tot;
+        } else {
+          // q at the chunk's last slot: ((E_{W-1} + C) + ex) + z
+          const uint32_t ew = (uint32_t)shfl((int)ex, W - 1);
+          agg_s = T::add(T::add(T::add(ew, s_last[0]), s_last[1]), s_last[2]);
+          if (l == 0) st_dev(&ws.w_tot[c], ((uint64_t)tag << 32) | agg_s);
+        }
+      }
+      if (flags & SF_COMPACT) {
+        const uint32_t a = l < W ? s_wcnt[l] : 0u;
+        uint32_t incl = a;
+        incl += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)incl);
+        incl += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)incl);
+        incl += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)incl);
+        incl += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)incl);
+        incl += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)incl);
+        s_coff[l] = incl - a;
+        agg_c = (uint32_t)bcast31((int)incl);
+      }
+      // look-backs inside the segment
+      if (flags & SF_SCAN) {
+        if constexpr (DT == COX_I32) {
+          const uint32_t pre = seg_lookback(c, lo, agg_s, ws.w_scan, tag, ws.hdr);
+          if (l == 0) s_pre_i = pre;
+        } else {
+          const double pre = seg_serial_f64(ws.w_tot, lo, c, tag, ws.hdr);
+          if (l == 0) s_pre_f = pre;
+        }
+      }
+      if (flags & SF_COMPACT) {
+        const uint32_t pre = seg_lookback(c, lo, agg_c, ws.w_cnt, tag, ws.hdr);
+        if (l == 0) s_pre_c = pre;
+        if (seg_count && c == lo + nchs - 1 && l == 0) seg_count[s] = (long long)pre + (long long)agg_c;
+      }
+      // segment total by the chunk that completes the segment's count
+      if (flags & SF_REDUCE) {
+        uint32_t d = 0u;
+        if (l == 0) d = add_dev32(&ws.done[s], 1u);
+        d = (uint32_t)__shfl((int)d, 0, 32);
+        if (d == nchs - 1) {
+          if constexpr (DT == COX_I32) {
+            const long long tot = seg_sum_i64(ws.w_part, lo, lo + nchs, tag, ws.hdr);
+            if (l == 0) ((long long *)seg_total)[s] = tot;
+          } else {
+            const double tot = seg_serial_f64(ws.w_part, lo, lo + nchs, tag, ws.hdr);
+            if (l == 0) ((double *)seg_total)[s] = tot;
+          }
+          if (l == 0) st_dev32(&ws.done[s], 0u);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- outputs
+    if (flags & SF_SCAN) {
+      const uint32_t E = w == 0 ? T::ident : s_E[w];
+      if constexpr (DT == COX_I32) {
+        const uint32_t pre = s_pre_i;
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+          const uint32_t base = T::add(T::add(E, cin[i]), exv[i]);
+#pragma unroll
+          for (int j = 0; j < V; j++) {
+            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
+            if (e < e1) y[e] = pre + T::add(base, z[i][j]);
+          }
+        }
+      } else {
+        const double pre = s_pre_f;
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+          const uint32_t base = T::add(T::add(E, cin[i]), exv[i]);
+#pragma unroll
+          for (int j = 0; j < V; j++) {
+            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
+            const float q = i2f((int)T::add(base, z[i][j]));
+            if (e < e1) y[e] = (uint32_t)f2i((float)(pre + (double)q));
+          }
+        }
+      }
+    }
+    if (flags & SF_COMPACT) {
+      const uint32_t *region = s_stage + w * 32 * K;
+      const uint32_t wcnt = s_wcnt[w];
+      const int64_t obase = s_obase + (int64_t)s_pre_c + s_coff[w];
+      for (uint32_t q = l; q < wcnt; q += 32) {
+        const int64_t pos = obase + q;
+        if (pos < e1) outc[pos] = region[q];  // bound: guards a failed wait only
+      }
+    }
+    __syncthreads();  // LDS reuse by the next chunk
+  }
+
+  if (threadIdx.x == 0) {
+    const uint32_t t = s_ticket;
+    if (t == (uint32_t)(NC + gridDim.x - 1)) {
+      // single-segment launch of an empty segment: identity outputs
+      if (nc_arg == 0) {
+        if ((flags & SF_REDUCE) && seg_total) {
+          if (DT == COX_I32) ((long long *)seg_total)[0] = 0;
+          else ((double *)seg_total)[0] = -0.0;
+        }
+        if ((flags & SF_COMPACT) && seg_count) seg_count[0] = 0;
+      }
+      st_dev32(&ws.hdr[HDR_TICKET], 0u);
+      st_dev32(&ws.hdr[HDR_EPOCH], epoch + 1u);
+    }
+  }
+}
+
+using seg_fn = void (*)(const uint32_t *, const int64_t *, int64_t, int64_t, int64_t, SegWS, void *, uint32_t *,
+                        uint32_t *, long long *, int);
+
+template <int DT>
+static seg_fn pick_seg_k(int k) {
+  switch (k) {
+  case 1: return k_segmented<1, DT>;
+  case 2: return k_segmented<2, DT>;
+  case 4: return k_segmented<4, DT>;
+  case 8: return k_segmented<8, DT>;
+  case 16: return k_segmented<16, DT>;
+  }
+  return nullptr;
+}
+static seg_fn pick_seg(int dt, int k) {
+  if (dt == COX_I32) return pick_seg_k<COX_I32>(k);
+  if (dt == COX_F32) return pick_seg_k<COX_F32>(k);
+  return nullptr;
+}
+
+struct SegCall {
+  const void *x;
+  cox_dtype dt;
+  const int64_t *off;
+  int64_t nseg, n;
+  void *seg_total, *y, *out;
+  int64_t *seg_count;
+  int flags;
+  Sigma sg;
+  SegWS ws;
+  seg_fn fn;
+  size_t lds;
+  int grid;
+};
+
+static cox_status seg_prepare(const void *x, cox_dtype dt, const int64_t *offsets, int64_t nseg, int64_t n,
+                              void *seg_total, void *y, void *out, int64_t *seg_count, int flags,
+                              const cox_cfg *cfg, void *ws, size_t ws_bytes, SegCall *sc) {
+  if (dt != COX_I32 && dt != COX_F32) return COX_ERR_DTYPE;
+  if (nseg < 0 || n < 0 || !offsets || !ws) return nseg < 0 || n < 0 ? COX_ERR_INVALID : !ws ? COX_ERR_WORKSPACE : COX_ERR_INVALID;
+  if ((flags & SF_REDUCE) && !seg_total) return COX_ERR_INVALID;
+  if ((flags & SF_SCAN) && !y && n > 0) return COX_ERR_INVALID;
+  if ((flags & SF_COMPACT) && (!seg_count || (!out && n > 0))) return COX_ERR_INVALID;
+  if (n > 0 && !x) return COX_ERR_INVALID;
+  if (n > 0 && !aligned16(x)) return COX_ERR_ALIGN;
+  Sigma sg;
+  cox_status st = resolve_cfg(COX_OP_SEGMENTED, dt, cfg, &sg);
+  if (st != COX_OK) return st;
+  if (sg.k > 16) return COX_ERR_UNSUPPORTED;
+  const int64_t S = (int64_t)32 * sg.W * sg.k;
+  const int64_t maxch = n / S + nseg + 1;
+  if (maxch > 0x7fffffffLL - 65536 || nseg > 0x7fffffffLL) return COX_ERR_INVALID;
+  size_t need = 0;
+  SegWS w = seg_layout(ws, nseg, maxch, &need);
+  if (ws_bytes < need) return COX_ERR_WORKSPACE;
+  seg_fn fn = pick_seg(dt, sg.k);
+  if (!fn) return COX_ERR_UNSUPPORTED;
+  const int block = 32 * sg.W;
+  const size_t lds = (flags & SF_COMPACT) ? (size_t)block * sg.k * 4 : 0;
+  if (lds + 1024 > device_max_lds()) return COX_ERR_UNSUPPORTED;
+  if (lds > 64 * 1024 &&
+      hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return COX_ERR_UNSUPPORTED;
+  sc->x = x;
+  sc->dt = dt;
+  sc->off = offsets;
+  sc->nseg = nseg;
+  sc->n = n;
+  sc->seg_total = seg_total;
+  sc->y = y;
+  sc->out = out;
+  sc->seg_count = seg_count;
+  sc->flags = flags;
+  sc->sg = sg;
+  sc->ws = w;
+  sc->fn = fn;
+  sc->lds = lds;
+  // default: as many blocks as fit, capped by the chunk bound
+  sc->grid = persistent_grid((const void *)fn, block, maxch, sg.G, lds);
+  return COX_OK;
+}
+
+static cox_status seg_launch(const SegCall &sc, hipStream_t st) {
+  const int block = 32 * sc.sg.W;
+  const int64_t S = (int64_t)block * sc.sg.k;
+  if (sc.nseg == 0) return COX_OK;
+  if (sc.dt == COX_I32)
+    hipLaunchKernelGGL(k_seg_setup<COX_I32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.ws,
+                       (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr,
+                       (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr);
+  else
+    hipLaunchKernelGGL(k_seg_setup<COX_F32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.ws,
+                       (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr,
+                       (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr);
+  cox_status r = launch_status();
+  if (r != COX_OK) return r;
+  int mg = (int)((sc.nseg * 32 + 255) / 256);
+  if (mg > 4096) mg = 4096;
+  hipLaunchKernelGGL(k_seg_map, dim3(mg), dim3(256), 0, st, sc.nseg, sc.ws);
+  r = launch_status();
+  if (r != COX_OK) return r;
+  hipLaunchKernelGGL(sc.fn, dim3(sc.grid), dim3(block), sc.lds, st, (const uint32_t *)sc.x, sc.off, sc.nseg, sc.n,
+                     (int64_t)-1, sc.ws, sc.seg_total, (uint32_t *)sc.y, (uint32_t *)sc.out,
+                     (long long *)sc.seg_count, sc.flags);
+  return launch_status();
+}
+
+}  // namespace cox
+
+using namespace cox;
+
+// ---------------------------------------------------------------- plans
+// A plan binds one segmented call (buffers, schedule, grid) to a captured
+// graph: the setup kernels and the fused kernel, replayed with one
+// hipGraphLaunch.  The graph holds kernel nodes only.
+struct cox_plan_s {
+  SegCall call;
+  hipStream_t own;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+namespace cox {
+
+// average time of `reps` launches of a prepared call on stream st (ms)
+static float time_call(const SegCall &sc, hipStream_t st, int reps) {
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess) return -1.0f;
+  if (hipEventCreate(&b) != hipSuccess) {
+    hipEventDestroy(a);
+    return -1.0f;
+  }
+  float ms = -1.0f;
+  if (seg_launch(sc, st) == COX_OK && hipEventRecord(a, st) == hipSuccess) {
+    bool ok = true;
+    for (int r = 0; r < reps && ok; r++) ok = seg_launch(sc, st) == COX_OK;
+    if (ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess &&
+        hipEventElapsedTime(&ms, a, b) == hipSuccess)
+      ms /= (float)reps;
+    else
+      ms = -1.0f;
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  return ms;
+}
+
+}  // namespace cox
+
+extern "C" {
+
+cox_status cox_segmented(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                         void *seg_total, void *y, void *out_compact, int64_t *seg_count, int which,
+                         const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+  if (which <= 0 || which > 7) return COX_ERR_INVALID;
+  SegCall sc;
+  cox_status st = seg_prepare(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count, which, cfg, ws,
+                              ws_bytes, &sc);
+  if (st != COX_OK) return st;
+  return seg_launch(sc, (hipStream_t)stream);
+}
+
+cox_status cox_segmented_reduce(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                                void *seg_total, const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+  return cox_segmented(x, dtype, offsets, nseg, n, seg_total, nullptr, nullptr, nullptr, SF_REDUCE, cfg, ws,
+                       ws_bytes, stream);
+}
+
+cox_status cox_segmented_scan(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                              void *y, const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+  return cox_segmented(x, dtype, offsets, nseg, n, nullptr, y, nullptr, nullptr, SF_SCAN, cfg, ws, ws_bytes,
+                       stream);
+}
+
+cox_status cox_segmented_compact(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                                 void *out_compact, int64_t *seg_count, const cox_cfg *cfg, void *ws,
+                                 size_t ws_bytes, void *stream) {
+  return cox_segmented(x, dtype, offsets, nseg, n, nullptr, nullptr, out_compact, seg_count, SF_COMPACT, cfg, ws,
+                       ws_bytes, stream);
+}
+
+cox_status cox_segmented_fused(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                               void *seg_total, void *y, void *out_compact, int64_t *seg_count, const cox_cfg *cfg,
+                               void *ws, size_t ws_bytes, void *stream) {
+  return cox_segmented(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count,
+                       SF_REDUCE | SF_SCAN | SF_COMPACT, cfg, ws, ws_bytes, stream);
+}
+
+cox_status cox_segmented_per_segment(const void *x, cox_dtype dtype, const int64_t *offsets,
+                                     const int64_t *offsets_host, int64_t nseg, int64_t n, void *seg_total, void *y,
+                                     void *out_compact, int64_t *seg_count, const cox_cfg *cfg, void *ws,
+                                     size_t ws_bytes, void *stream) {
+  if (!offsets_host) return COX_ERR_INVALID;
+  SegCall sc;
+  const int flags = SF_REDUCE | SF_SCAN | SF_COMPACT;
+  cox_status st = seg_prepare(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count, flags, cfg, ws,
+                              ws_bytes, &sc);
+  if (st != COX_OK) return st;
+  const int block = 32 * sc.sg.W;
+  const int64_t S = (int64_t)block * sc.sg.k;
+  const size_t esz = 8;  // seg_total entries are int64 or double
+  for (int64_t s = 0; s <= nseg; s++)
+    if (offsets_host[s] < 0 || offsets_host[s] > n || (s > 0 && offsets_host[s] < offsets_host[s - 1]))
+      return COX_ERR_INVALID;
+  for (int64_t s = 0; s < nseg; s++) {
+    const int64_t len = offsets_host[s + 1] - offsets_host[s];
+    const int64_t nc = (len + S - 1) / S;
+    int grid = (int)(nc < sc.grid ? nc : sc.grid);
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(sc.fn, dim3(grid), dim3(block), sc.lds, (hipStream_t)stream, (const uint32_t *)x,
+                       offsets + s, (int64_t)1, n, nc, sc.ws, (void *)((char *)seg_total + esz * s), (uint32_t *)y,
+                       (uint32_t *)out_compact, (long long *)(seg_count + s), flags);
+    st = launch_status();
+    if (st != COX_OK) return st;
+  }
+  return COX_OK;
+}
+
+cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
+                              void *seg_total, void *y, void *out_compact, int64_t *seg_count, int which,
+                              const cox_cfg *cfg, int autotune, void *ws, size_t ws_bytes, void *stream,
+                              cox_plan *plan) {
+  if (!plan) return COX_ERR_INVALID;
+  *plan = nullptr;
+  if (which <= 0 || which > 7) return COX_ERR_INVALID;
+  SegCall best;
+  cox_status st = seg_prepare(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count, which, cfg, ws,
+                              ws_bytes, &best);
+  if (st != COX_OK) return st;
+  cox_plan p = (cox_plan)calloc(1, sizeof(cox_plan_s));
+  if (!p) return COX_ERR_INVALID;
+  hipError_t e = hipStreamCreateWithFlags(&p->own, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    free(p);
+    set_hip_error(e);
+    return COX_ERR_HIP;
+  }
+  // the plan's stream starts after the caller's pending work
+  hipEvent_t ready;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess) {
+    hipEventRecord(ready, (hipStream_t)stream);
+    hipStreamWaitEvent(p->own, ready, 0);
+    hipEventDestroy(ready);
+  }
+  const bool tune = autotune && (!cfg || (!cfg->items_per_lane && !cfg->warps_per_block));
+  if (tune) {
+    // candidate schedules and grids, timed on the caller's buffers
+    static const int KW[][2] = {{2, 16}, {4, 8}, {4, 16}, {8, 4}, {8, 8}, {8, 16}, {16, 4}, {16, 8}};
+    const int cus = device_cus();
+    float best_ms = -1.0f;
+    for (const auto &kw : KW) {
+      for (int gpc : {0, 2, 4}) {
+        cox_cfg c;
+        c.items_per_lane = kw[0];
+        c.warps_per_block = kw[1];
+        c.grid_blocks = gpc * cus;
+        c.reserved = 0;
+        SegCall cand;
+        if (seg_prepare(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count, which, &c, ws, ws_bytes,
+                        &cand) != COX_OK)
+          continue;
+        const float ms = time_call(cand, p->own, 3);
+        if (ms > 0.0f && (best_ms < 0.0f || ms < best_ms)) {
+          best_ms = ms;
+          best = cand;
+        }
+      }
+    }
+  }
+  p->call = best;
+  e = hipStreamBeginCapture(p->own, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    st = seg_launch(best, p->own);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(p->own, &g);
+    if (st == COX_OK && e2 != hipSuccess) {
+      set_hip_error(e2);
+      st = COX_ERR_HIP;
+    }
+    p->graph = g;
+    if (st == COX_OK) {
+      e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        set_hip_error(e);
+        st = COX_ERR_HIP;
+      }
+    }
+  } else {
+    set_hip_error(e);
+    st = COX_ERR_HIP;
+  }
+  if (st == COX_OK) {
+    e = hipStreamSynchronize(p->own);
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      st = COX_ERR_HIP;
+    }
+  }
+  if (st != COX_OK) {
+    cox_plan_destroy(p);
+    return st;
+  }
+  *plan = p;
+  return COX_OK;
+}
+
+cox_status cox_plan_execute(cox_plan plan, void *stream) {
+  if (!plan || !plan->exec) return COX_ERR_INVALID;
+  const hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return COX_ERR_HIP;
+  }
+  return COX_OK;
+}
+
+cox_status cox_plan_get_cfg(cox_plan plan, cox_cfg *cfg) {
+  if (!plan || !cfg) return COX_ERR_INVALID;
+  cfg->items_per_lane = plan->call.sg.k;
+  cfg->warps_per_block = plan->call.sg.W;
+  cfg->grid_blocks = plan->call.grid;
+  cfg->reserved = 0;
+  return COX_OK;
+}
+
+cox_status cox_plan_destroy(cox_plan plan) {
+  if (!plan) return COX_OK;
+  if (plan->exec) hipGraphExecDestroy(plan->exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  if (plan->own) {
+    hipStreamSynchronize(plan->own);
+    hipStreamDestroy(plan->own);
+  }
+  free(plan);
+  return COX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+"""GPU parity of the segmented batched path (fused persistent kernel, its
+single-output variants, the per-segment baseline and graph-captured
+plans) against the oracle, bit for bit, on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from paper_2112_10034_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SIGMAS = [(1, 1), (4, 8), (8, 4), (16, 8), (2, 16), (8, 16), (16, 4)]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2112_10034_amd import cox
+
+    cox.lib()
+    return torch, cox
+
+
+def small_case():
+    """Empty, length-1, ragged and many-chunk segments, plus one segment
+    that does not start on a 16-byte boundary."""
+    off = np.array([0, 0, 1, 5000, 5000, 9000, 20000, 20001, 31000, 31003, 31003 + 4097 * 3 + 11], np.int64)
+    xi, xf = inputs.segment_values(int(off[-1]))
+    return off, xi, xf
+
+
+def bits(a):
+    a = np.asarray(a)
+    return a.view(np.uint64) if a.dtype.itemsize == 8 else a.view(np.uint32)
+
+
+def check(torch, got, want, nseg):
+    tot, y, oc, cnt = [None if g is None else g.cpu().numpy() for g in got]
+    wt, wy, woc, wcnt = want
+    assert np.array_equal(bits(tot), bits(wt)), "segment totals"
+    assert np.array_equal(bits(y), bits(wy)), "segmented scan"
+    assert np.array_equal(cnt, wcnt), "kept counts"
+    assert np.array_equal(bits(oc), bits(woc)), "compacted output"
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+@pytest.mark.parametrize("k,W", SIGMAS)
+def test_segmented_fused_bit_exact(dev, oracle_mod, dtype, k, W):
+    torch, cox = dev
+    off, xi, xf = small_case()
+    x = xi if dtype == "i32" else xf
+    print("segmented", dtype, k, W, flush=True)
+    got = cox.segmented(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(), 7, cfg=(k, W))
+    check(torch, got, oracle_mod.segmented(x, off, k, W), off.size - 1)
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_segmented_single_outputs_match_fused(dev, oracle_mod, dtype):
+    torch, cox = dev
+    off, xi, xf = small_case()
+    x = xi if dtype == "i32" else xf
+    xg, og = torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda()
+    wt, wy, woc, wcnt = oracle_mod.segmented(x, off, 4, 8)
+    t, _, _, _ = cox.segmented(xg, og, cox.SEG_REDUCE, cfg=(4, 8))
+    assert np.array_equal(bits(t.cpu().numpy()), bits(wt))
+    _, y, _, _ = cox.segmented(xg, og, cox.SEG_SCAN, cfg=(4, 8))
+    assert np.array_equal(bits(y.cpu().numpy()), bits(wy))
+    _, _, oc, cnt = cox.segmented(xg, og, cox.SEG_COMPACT, cfg=(4, 8))
+    assert np.array_equal(cnt.cpu().numpy(), wcnt) and np.array_equal(bits(oc.cpu().numpy()), bits(woc))
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_per_segment_baseline_matches_oracle(dev, oracle_mod, dtype):
+    torch, cox = dev
+    off, xi, xf = small_case()
+    x = xi if dtype == "i32" else xf
+    got = cox.segmented_per_segment(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(),
+                                    torch.from_numpy(off), cfg=(8, 8))
+    check(torch, got, oracle_mod.segmented(x, off, 8, 8), off.size - 1)
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_plan_graph_replays(dev, oracle_mod, dtype):
+    """An autotuned plan replayed several times, with eager work and
+    synchronisations between replays; every replay is checked."""
+    torch, cox = dev
+    off, xi, xf = small_case()
+    x = xi if dtype == "i32" else xf
+    xg, og = torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda()
+    plan = cox.Plan(xg, og, 7, autotune=True)
+    k, W, G = plan.cfg()
+    print("plan sigma", k, W, G, flush=True)
+    want = oracle_mod.segmented(x, off, k, W)
+    for rep in range(4):
+        for t in (plan.seg_total, plan.y, plan.out, plan.seg_count):
+            t.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        got = plan.execute()
+        torch.cuda.synchronize()
+        check(torch, got, want, off.size - 1)
+        assert torch.isfinite(junk)
+    plan.close()
+
+
+def test_plan_fixed_schedule_and_reuse_with_other_calls(dev, oracle_mod):
+    torch, cox = dev
+    off, xi, _ = small_case()
+    xg, og = torch.from_numpy(xi).cuda(), torch.from_numpy(off).cuda()
+    plan = cox.Plan(xg, og, 7, cfg=(8, 4), autotune=False)
+    assert plan.cfg()[:2] == (8, 4)
+    want = oracle_mod.segmented(xi, off, 8, 4)
+    for _ in range(3):
+        cox.segmented(xg, og, 7, cfg=(16, 8))  # other calls on their own workspace in between
+        check(torch, plan.execute(), want, off.size - 1)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_segmented_full_workload(dev, oracle_mod, dtype):
+    """The full batching workload (10,000 lognormal segments) with the
+    default schedule, compared element by element with the oracle."""
+    torch, cox = dev
+    off = inputs.segment_offsets()
+    xi, xf = inputs.segment_values(int(off[-1]))
+    x = xi if dtype == "i32" else xf
+    k, W, _ = cox.default_cfg(cox.OP_SEGMENTED, cox.I32 if dtype == "i32" else cox.F32)
+    print("full segmented", dtype, "n", off[-1], "sigma", k, W, flush=True)
+    got = cox.segmented(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(), 7)
+    want = oracle_mod.segmented(x, off, k, W)
+    check(torch, got, want, off.size - 1)
