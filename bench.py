@@ -87,6 +87,61 @@ def cpu_baseline(x, keys, f, sample, sig):
                       f", all five primitives once ({dt:.1f} s wall on {cores} threads)"}
 
 
+def batching(reps=5, base_reps=2):
+    """The segmented workload (10,000 lognormal segments): the fused
+    reduce + scan + compaction as one autotuned graph-captured launch vs the
+    same kernel launched once per segment, per dtype."""
+    import numpy as np
+    import torch
+
+    from paper_2112_10034_amd import cox, inputs
+
+    off = inputs.segment_offsets()
+    n = int(off[-1])
+    nseg = off.size - 1
+    xi, xf = inputs.segment_values(n)
+    og = torch.from_numpy(off).cuda()
+    res = {"workload": f"{nseg} segments, lognormal lengths (median 2000, cap 2^20), {n} elements per dtype; "
+                       "segmented sum + inclusive scan + compaction (x > 0) fused",
+           "n": n, "nseg": nseg}
+
+    def timed(fn, r):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(r):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / r
+
+    for name, arr in (("i32", xi), ("f32", xf)):
+        xg = torch.from_numpy(arr).cuda()
+        plan = cox.Plan(xg, og, 7, autotune=True)
+        k, W, G = plan.cfg()
+        t_plan = timed(plan.execute, reps)
+        kept = int(plan.seg_count.sum().item())
+        alg = 4 * n + 4 * n + 4 * kept + 8 * (nseg + 1) + 16 * nseg
+        tot, y, oc, cnt = (torch.empty_like(plan.seg_total), torch.empty_like(plan.y), torch.empty_like(plan.out),
+                           torch.empty_like(plan.seg_count))
+        t_seg = timed(lambda: cox.segmented_per_segment(xg, og, torch.from_numpy(off), cfg=(k, W), seg_total=tot,
+                                                        y=y, out=oc, seg_count=cnt), base_reps)
+        same = bool(torch.equal(cnt, plan.seg_count))
+        plan.close()
+        for ws in cox._ws_cache.values():
+            ws.status()
+        res[name] = {"sigma": [k, W], "grid": G, "batched_ms": round(t_plan, 4),
+                     "batched_gelem_s": round(n / (t_plan * 1e-3) / 1e9, 2),
+                     "batched_gb_s": round(alg / (t_plan * 1e-3) / 1e9, 1),
+                     "batched_hbm_frac": round(alg / (t_plan * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "per_segment_ms": round(t_seg, 3), "speedup": round(t_seg / t_plan, 2),
+                     "counts_agree": same}
+        log(f"batching {name}: plan {t_plan:.3f} ms, per-segment {t_seg:.2f} ms")
+        del xg
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +151,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 28,
                     help="elements of each input the oracle runs on (default: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batching", action="store_true", help="skip the segmented batching comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -240,6 +296,10 @@ def main():
         "roofline": roof,
         "reference": reference,
     }
+    if not args.no_batching:
+        del xg, kg, fg, y, cout, srt
+        torch.cuda.empty_cache()
+        out["batching"] = batching()
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, n)
         log(f"cpu baseline: oracle on {sample} elements")

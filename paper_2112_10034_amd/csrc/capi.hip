@@ -209,12 +209,9 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
   case COX_OP_SCAN:
   case COX_OP_COMPACT: return WS_HEADER + 8 * (size_t)(nch + 1);
   case COX_OP_SEGMENTED: {
-    // chunks of every segment (each segment rounds up): chunk starts and
-    // done counters per segment, a map word and four status words per chunk
+    // chunks of every segment (each segment rounds up)
     if (nseg < 0) return 0;
-    const int64_t maxch = n / S + nseg + 1;
-    return WS_HEADER + 4 * (size_t)(nseg + 1) + 8 + 4 * (size_t)nseg + 8 + 4 * (size_t)maxch + 8 +
-           32 * (size_t)maxch;
+    return seg_workspace_bytes(nseg, n / S + nseg + 1);
   }
   }
   return 0;

@@ -98,5 +98,7 @@ struct Sigma {
   int k, W, G;
 };
 cox_status resolve_cfg(cox_op op, cox_dtype dt, const cox_cfg *cfg, Sigma *out);
+// workspace bytes of a segmented call over nseg segments and at most maxch chunks
+size_t seg_workspace_bytes(int64_t nseg, int64_t maxch);
 
 }  // namespace cox

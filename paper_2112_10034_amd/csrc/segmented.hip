@@ -24,9 +24,12 @@
 //  - int32 scan carry and compaction offsets: decoupled look-back bounded
 //    below by the segment's first chunk;
 //  - float scan carry C_j: the FP64 sum, in chunk order from -0.0, of the
-//    earlier chunks' totals T (q at the chunk's last slot), each chunk
-//    reading the published totals of its predecessors; output
-//    (float)(C_j + (double)q);
+//    earlier chunks' totals T (q at the chunk's last slot); output
+//    (float)(C_j + (double)q).  A serial left-to-right sum continues
+//    exactly from any of its prefixes, so each chunk publishes its
+//    inclusive FP64 prefix C_j + T_j and a later chunk starts from the
+//    nearest published prefix and adds the totals after it in order: a
+//    decoupled look-back whose result is the serial sum bit for bit;
 //  - totals: every chunk publishes P and counts itself in the segment's
 //    done counter; the chunk completing the count adds the segment's
 //    partials (int64 sum, or FP64 serial ascending from -0.0).
@@ -52,6 +55,8 @@ struct SegWS {
   uint64_t *w_cnt;        // maxch: look-back words of kept counts
   uint64_t *w_part;       // maxch: [tag | bits] reduce partials
   uint64_t *w_tot;        // maxch: [tag | bits] float chunk scan totals
+  uint64_t *w_ph;         // maxch: [tag | high half] FP64 inclusive prefixes
+  uint64_t *w_pl;         // maxch: [tag | low half]
 };
 
 static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
@@ -76,8 +81,18 @@ static SegWS seg_layout(void *ws, int64_t nseg, int64_t maxch, size_t *bytes) {
   o += 8 * (size_t)maxch;
   w.w_tot = (uint64_t *)(p + o);
   o += 8 * (size_t)maxch;
+  w.w_ph = (uint64_t *)(p + o);
+  o += 8 * (size_t)maxch;
+  w.w_pl = (uint64_t *)(p + o);
+  o += 8 * (size_t)maxch;
   if (bytes) *bytes = o;
   return w;
+}
+
+size_t seg_workspace_bytes(int64_t nseg, int64_t maxch) {
+  size_t b = 0;
+  seg_layout(nullptr, nseg, maxch, &b);
+  return b;
 }
 
 enum : int { SF_REDUCE = 1, SF_SCAN = 2, SF_COMPACT = 4 };
@@ -287,6 +302,53 @@ __device__ double seg_serial_f64(const uint64_t *p, int64_t a, int64_t b, uint32
   return acc;
 }
 
+// float scan carry of chunk c (warp 0): the FP64 sum from -0.0, in chunk
+// order, of the totals T of chunks lo..c-1, taken from the nearest earlier
+// chunk that has published its inclusive prefix; then publishes this
+// chunk's inclusive prefix carry + T_c.  The window is the 32 chunks below
+// c, re-read until one of them (or the segment start) has a prefix.
+__device__ double seg_lookback_f64(int64_t c, int64_t lo, uint32_t tc, const SegWS &ws, uint32_t tag) {
+  const int l = llane();
+  double carry = -0.0;
+  if (c > lo) {
+    const int64_t idx = c - 1 - l;
+    uint32_t spins = 0;
+    for (;;) {
+      bool pref = idx < lo;  // the segment start acts as the prefix -0.0
+      double pv = -0.0;
+      float tv = -0.0f;
+      if (!pref) {
+        const uint64_t h = ld_dev(&ws.w_ph[idx]), lw = ld_dev(&ws.w_pl[idx]);
+        if ((uint32_t)(h >> 32) == tag && (uint32_t)(lw >> 32) == tag) {
+          pref = true;
+          pv = __hiloint2double((int)(uint32_t)h, (int)(uint32_t)lw);
+        } else {
+          tv = i2f((int)(uint32_t)seg_word(ws.w_tot, idx, tag, ws.hdr));
+        }
+      }
+      const uint32_t pm = ballot(pref);
+      if (pm) {
+        const int p = __builtin_ctz(pm);
+        double acc = __shfl(pv, p, 32);
+        for (int j = p - 1; j >= 0; j--) acc = acc + (double)__shfl(tv, j, 32);
+        carry = acc;
+        break;
+      }
+      if (++spins >= MAX_SPIN || ((spins & 1023u) == 0u && ld_dev32(&ws.hdr[HDR_ERR]) == tag)) {
+        if (l == 0) st_dev32(&ws.hdr[HDR_ERR], tag);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  const double pc = carry + (double)i2f((int)tc);
+  if (l == 0) {
+    st_dev(&ws.w_ph[c], ((uint64_t)tag << 32) | (uint32_t)__double2hiint(pc));
+    st_dev(&ws.w_pl[c], ((uint64_t)tag << 32) | (uint32_t)__double2loint(pc));
+  }
+  return carry;
+}
+
 // int64 sum of the int32 bits in words [a, b) (warp 0)
 __device__ long long seg_sum_i64(const uint64_t *p, int64_t a, int64_t b, uint32_t tag, uint32_t *hdr) {
   const int l = llane();
@@ -473,7 +535,7 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
           const uint32_t pre = seg_lookback(c, lo, agg_s, ws.w_scan, tag, ws.hdr);
           if (l == 0) s_pre_i = pre;
         } else {
-          const double pre = seg_serial_f64(ws.w_tot, lo, c, tag, ws.hdr);
+          const double pre = seg_lookback_f64(c, lo, agg_s, ws, tag);
           if (l == 0) s_pre_f = pre;
         }
       }

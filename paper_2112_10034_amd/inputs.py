@@ -76,9 +76,22 @@ def _loguniform(g, m):
     return np.power(10.0, g.uniform(-3.0, 3.0, size=m))
 
 
-def _cond(terms64):
-    s = float(np.sum(terms64, dtype=np.float64))
-    return float(np.sum(np.abs(terms64), dtype=np.float64)) / max(abs(s), 1e-300)
+_BLK = 1 << 20  # elements per block of the precision generator's passes
+
+
+def _slices(m):
+    for a in range(0, m, _BLK):
+        yield slice(a, min(a + _BLK, m))
+
+
+def _scatter(parts, perm):
+    """The concatenation of ``parts``, element j placed at position perm[j]."""
+    out = np.empty(perm.size, parts[0].dtype)
+    o = 0
+    for p in parts:
+        out[perm[o:o + p.size]] = p
+        o += p.size
+    return out
 
 
 def precision_inputs(n=FULL_N[3], seed=None, target=1e8, kind="sum", dtype="f32"):
@@ -89,87 +102,119 @@ def precision_inputs(n=FULL_N[3], seed=None, target=1e8, kind="sum", dtype="f32"
     -fl32(x_i (1 + eps u_i)), u_i ~ U(-1, 1), and eps is rescaled until the
     measured condition number is within a factor 2 of ``target``.
     bfloat16: the partner is -x_i, with its magnitude moved by one bfloat16
-    ulp (random direction) on the fraction f of the pairs with the smallest
-    u_i; f is chosen so that the condition number is closest to the target.
-    Dots pair (a, b) with (-a, b') where b' is b perturbed the same way.  The arrays are
-    shuffled with a seeded permutation.  ``info`` records eps or f and the
-    achieved condition number, measured in float64 (the exact reference
-    comes from the oracle's exact accumulator, not from here).
+    ulp (random direction) on the first j pairs (pairs are i.i.d., so these
+    are a random subset); j is the prefix whose condition number is closest
+    to the target.  Dots pair (a, b) with (-a, b') where b' is b perturbed
+    the same way.  The pairs' elements are scattered to the positions of one
+    seeded shuffle of 0..n-1.  ``info`` records eps or j / (n/2) and the
+    achieved condition number sum|t| / |sum t| over the terms t, summed in
+    float64 pair by pair (the exact reference comes from the oracle's exact
+    accumulator, not from here).  The passes run over blocks of 2^20 pairs
+    so that full-size inputs need few large temporaries.
     """
     assert n % 2 == 0
     h = n // 2
     g_mag, g_sgn, g_del, g_perm, g_b, g_dir = _streams(3, 6, seed)
-    mag = _loguniform(g_mag, h)
-    sgn = np.where(g_sgn.integers(0, 2, size=h) == 1, 1.0, -1.0)
+    mag = g_mag.uniform(-3.0, 3.0, size=h)
+    np.power(10.0, mag, out=mag)
+    np.negative(mag, out=mag, where=g_sgn.integers(0, 2, size=h, dtype=np.uint8) == 0)
     u = g_del.uniform(-1.0, 1.0, size=h)
-    perm = g_perm.permutation(n)
-    bmag = _loguniform(g_b, h) if kind == "dot" else None
-    ddir = np.where(g_dir.integers(0, 2, size=h) == 1, 1, -1).astype(np.int32)
+    perm = np.arange(n, dtype=np.int32 if n < (1 << 31) else np.int64)
+    g_perm.shuffle(perm)
+    bmag = None
+    if kind == "dot":
+        bmag = g_b.uniform(-3.0, 3.0, size=h)
+        np.power(10.0, bmag, out=bmag)
+    ddir = (g_dir.integers(0, 2, size=h, dtype=np.int8) * 2 - 1).astype(np.int8)
 
     if dtype == "f32":
-        xa = (sgn * mag).astype(np.float32)
+        xa = mag.astype(np.float32)
         bb = bmag.astype(np.float32) if kind == "dot" else None
+        del mag, bmag
 
-        def build(eps):
-            if kind == "sum":
-                xp = (-(xa.astype(np.float64) * (1.0 + eps * u))).astype(np.float32)
-                v = np.concatenate([xa, xp])[perm]
-                return (v,), v.astype(np.float64)
-            a = np.concatenate([xa, -xa])[perm]
-            bp = (bb.astype(np.float64) * (1.0 + eps * u)).astype(np.float32)
-            b = np.concatenate([bb, bp])[perm]
-            return (a, b), a.astype(np.float64) * b.astype(np.float64)
+        def build(eps, keep):
+            # float32 x float32 products and sums of two float32 are exact in float64
+            part = np.empty(h, np.float32) if keep else None
+            tot = absum = 0.0
+            for sl in _slices(h):
+                x64 = xa[sl].astype(np.float64)
+                f = 1.0 + eps * u[sl]
+                if kind == "sum":
+                    q = (-(x64 * f)).astype(np.float32)
+                    q64 = q.astype(np.float64)
+                    tot += float(np.sum(x64 + q64))
+                    absum += float(np.abs(x64).sum() + np.abs(q64).sum())
+                else:
+                    b64 = bb[sl].astype(np.float64)
+                    q = (b64 * f).astype(np.float32)
+                    q64 = q.astype(np.float64)
+                    tot += float(np.sum(x64 * b64 - x64 * q64))
+                    absum += float((np.abs(x64) * (b64 + q64)).sum())
+                if keep:
+                    part[sl] = q
+            return part, absum / max(abs(tot), 1e-300)
 
         # cond ~ 1/eps: rescale until within a factor 2 of the target
         p = 1e-4
-        for _ in range(6):
-            arrs, t = build(p)
-            c = _cond(t)
-            if target / 2 <= c <= target * 2:
+        for it in range(6):
+            _, c = build(p, False)
+            if target / 2 <= c <= target * 2 or it == 5:
                 break
             p = p * c / target
+        part, c = build(p, True)
         info = {"param": p, "cond": c, "kind": kind, "dtype": dtype}
-        return (*arrs, info)
+        if kind == "sum":
+            return _scatter([xa, part], perm), info
+        return _scatter([xa, -xa], perm), _scatter([bb, part], perm), info
 
     # bfloat16: pair i is nudged (its partner's magnitude moved by one
-    # bfloat16 ulp in direction ddir_i) iff u_i is below a threshold.  Each
-    # pair contributes c_i to the sum (0 when not nudged), so ordering the
-    # pairs by u turns the sum into a prefix sum; the threshold is the
-    # prefix whose condition number is closest to the target.
-    xa = _to_bf16_bits((sgn * mag).astype(np.float32))
+    # bfloat16 ulp in direction ddir_i) iff i < j.  Each pair contributes c_i
+    # to the sum (0 when not nudged), so the sum over the first j pairs is a
+    # prefix sum; j is the prefix whose condition number is closest to the
+    # target.
+    xa = _to_bf16_bits(mag.astype(np.float32))
     bb = _to_bf16_bits(bmag.astype(np.float32)) if kind == "dot" else None
+    del mag, bmag
+
+    def terms(sl, step):
+        """float64 pair terms (first, partner) of pairs sl with the given nudges."""
+        x64 = bf16_to_f32(xa[sl]).astype(np.float64)
+        if kind == "sum":
+            q = ((xa[sl] ^ 0x8000).astype(np.int32) + step).astype(np.uint16)  # -(x_i +/- 1 ulp)
+            return x64, bf16_to_f32(q).astype(np.float64)
+        b64 = bf16_to_f32(bb[sl]).astype(np.float64)
+        q = (bb[sl].astype(np.int32) + step).astype(np.uint16)
+        return x64 * b64, -x64 * bf16_to_f32(q).astype(np.float64)
+
+    absum = 0.0
+    for sl in _slices(h):
+        t0, _ = terms(sl, 0)
+        absum += 2.0 * float(np.abs(t0).sum())
+    best, j, run = np.inf, 1, 0.0
+    for sl in _slices(h):
+        t0, t1 = terms(sl, ddir[sl])
+        _, z1 = terms(sl, 0)
+        pref = np.abs(run + np.cumsum((t0 + t1) - (t0 + z1)))
+        run = run + float(np.sum((t0 + t1) - (t0 + z1)))
+        with np.errstate(divide="ignore"):
+            score = np.abs(np.log(np.maximum(pref, 1e-300) * target / absum))
+        i = int(np.argmin(score))
+        if score[i] < best:
+            best, j = float(score[i]), sl.start + i + 1
+    step = np.zeros(h, np.int8)
+    step[:j] = ddir[:j]
+    part = np.empty(h, np.uint16)
+    tot = absum = 0.0
+    for sl in _slices(h):
+        t0, t1 = terms(sl, step[sl])
+        tot += float(np.sum(t0 + t1))
+        absum += float(np.abs(t0).sum() + np.abs(t1).sum())
+        part[sl] = ((xa[sl] ^ 0x8000).astype(np.int32) + step[sl]).astype(np.uint16) if kind == "sum" else \
+            (bb[sl].astype(np.int32) + step[sl]).astype(np.uint16)
+    info = {"param": j / h, "cond": absum / max(abs(tot), 1e-300), "kind": kind, "dtype": dtype}
     if kind == "sum":
-        xa64 = bf16_to_f32(xa).astype(np.float64)
-        moved = (xa.astype(np.int32) + ddir).astype(np.uint16)
-        contrib = xa64 - bf16_to_f32(moved).astype(np.float64)
-        absum = 2.0 * np.abs(xa64).sum()
-    else:
-        a64 = bf16_to_f32(xa).astype(np.float64)
-        b64 = bf16_to_f32(bb).astype(np.float64)
-        moved = (bb.astype(np.int32) + ddir).astype(np.uint16)
-        contrib = a64 * b64 - a64 * bf16_to_f32(moved).astype(np.float64)
-        absum = 2.0 * np.abs(a64 * b64).sum()
-    order = np.argsort(u, kind="stable")
-    pref = np.abs(np.cumsum(contrib[order]))
-    with np.errstate(divide="ignore"):
-        score = np.abs(np.log(np.maximum(pref, 1e-300) * target / absum))
-    j = int(np.argmin(score)) + 1
-    nudged = np.zeros(h, bool)
-    nudged[order[:j]] = True
-    step = np.where(nudged, ddir, 0).astype(np.int32)
-    if kind == "sum":
-        xp = ((xa ^ 0x8000).astype(np.int32) + step).astype(np.uint16)  # -(x_i +/- 1 ulp)
-        v = np.concatenate([xa, xp])[perm]
-        t = bf16_to_f32(v).astype(np.float64)
-        arrs = (v,)
-    else:
-        a = np.concatenate([xa, xa ^ 0x8000])[perm]
-        bp = (bb.astype(np.int32) + step).astype(np.uint16)
-        b = np.concatenate([bb, bp])[perm]
-        t = bf16_to_f32(a).astype(np.float64) * bf16_to_f32(b).astype(np.float64)
-        arrs = (a, b)
-    info = {"param": j / h, "cond": _cond(t), "kind": kind, "dtype": dtype}
-    return (*arrs, info)
+        return _scatter([xa, part], perm), info
+    return _scatter([xa, xa ^ 0x8000], perm), _scatter([bb, part], perm), info
 
 
 def segment_offsets(nseg=NSEG, seed=None, median=SEG_MEDIAN, sigma=SEG_SIGMA, cap=SEG_CAP):
