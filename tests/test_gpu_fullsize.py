@@ -1,0 +1,152 @@
+"""Full-size GPU parity.
+
+1. The primitive set at 2^28 elements in the launch configuration the
+   throughput benchmark times (default schedules and grids, the 4-keys-per-
+   lane tile sort), compared element by element with the oracle.
+2. The 2^28-element precision workload (FP32 and BF16, sum and dot, plain
+   and TwoSum accumulation, default schedule): bit-exact against the oracle
+   on the same schedule, and the error of every result against the exact
+   sum (rounded once to FP64) stated and checked against its a-priori bound.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2112_10034_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+N = 1 << 28
+U32 = 2.0 ** -24
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2112_10034_amd import cox
+
+    cox.lib()
+    return torch, cox
+
+
+@pytest.fixture(scope="module")
+def prim():
+    print("generating the 2^28 primitive-set inputs", flush=True)
+    return inputs.primitive_inputs(N)
+
+
+def up(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def down(t):
+    return t.cpu().numpy()
+
+
+def test_full_reduce_i32_and_f32(dev, oracle_mod, prim):
+    torch, cox = dev
+    x, _, f = prim
+    k, W, _ = cox.default_cfg(cox.OP_REDUCE, cox.I32)
+    print("full reduce i32 sigma", k, W, flush=True)
+    t, p = cox.warp_reduce(up(torch, x))
+    op, ot = oracle_mod.reduce(x, k, W)
+    assert np.array_equal(down(p), op)
+    assert int(down(t)[0]) == ot == int(x.astype(np.int64).sum())
+    k, W, _ = cox.default_cfg(cox.OP_REDUCE, cox.F32)
+    print("full reduce f32 sigma", k, W, flush=True)
+    t, p = cox.warp_reduce(up(torch, f))
+    op, ot = oracle_mod.reduce(f, k, W)
+    assert np.array_equal(down(p).view(np.uint32), op.view(np.uint32))
+    assert down(t).view(np.uint64)[0] == np.float64(ot).view(np.uint64)
+
+
+def test_full_scan(dev, oracle_mod, prim):
+    torch, cox = dev
+    x = prim[0]
+    k, W, _ = cox.default_cfg(cox.OP_SCAN)
+    print("full scan sigma", k, W, flush=True)
+    y = down(cox.warp_scan(up(torch, x)))
+    assert np.array_equal(y, oracle_mod.scan_i32(x, k, W))
+    cox.workspace(cox.OP_SCAN, cox.I32, N).status()
+
+
+def test_full_compaction(dev, oracle_mod, prim):
+    torch, cox = dev
+    x = prim[0]
+    k, W, _ = cox.default_cfg(cox.OP_COMPACT)
+    print("full compaction sigma", k, W, flush=True)
+    out, cnt = cox.ballot_compact(up(torch, x))
+    want, wcnt = oracle_mod.compact_i32(x, k, W)
+    c = int(down(cnt)[0])
+    assert c == wcnt == int((x > 0).sum())
+    assert np.array_equal(down(out[:c]), want)
+    cox.workspace(cox.OP_COMPACT, cox.I32, N).status()
+
+
+def test_full_tile_sort(dev, oracle_mod, prim):
+    torch, cox = dev
+    keys = prim[1]
+    print("full tile sort, 4 keys per lane", flush=True)
+    got = down(cox.tile_sort(up(torch, keys.view(np.int32)), cfg=(4, 0))).view(np.uint32)
+    assert np.array_equal(got, oracle_mod.tile_sort_u32(keys))
+
+
+def _bounds(k, W, nch, absum, exact):
+    """A-priori bounds on |result - exact|.  Plain: each chunk partial is a
+    tree of at most h = k + 10 FP32 additions (k lane-serial, 5 warp, 5
+    block levels; identity padding is exact), gamma_h * sum|terms|, plus
+    the FP64 final over nch partials.  TwoSum (Ogita-Rump-Oishi Sum2 /
+    Dot2 per chunk, pairs combined in FP64): u * |chunk sum| per partial is
+    the dominant rounding of the compensated chunk value, so
+    u * sum|terms| is a safe bound for all chunks together, plus
+    gamma_h^2 * sum|terms| and the FP64 final."""
+    h = k + 10
+    g = h * U32 / (1 - h * U32)
+    fp64 = (nch + 10) * U64 * absum
+    plain = g * absum + fp64
+    comp = U32 * abs(exact) + 4 * g * g * absum + fp64
+    return plain, comp
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("kind", ["sum", "dot"])
+def test_full_precision(dev, oracle_mod, dtype, kind):
+    torch, cox = dev
+    print("generating 2^28 precision inputs", dtype, kind, flush=True)
+    arrs = inputs.precision_inputs(N, kind=kind, dtype=dtype)
+    data, info = arrs[:-1], arrs[-1]
+    tdt = torch.bfloat16 if dtype == "bf16" else torch.float32
+    g = [up(torch, a).view(tdt) if dtype == "bf16" else up(torch, a) for a in data]
+    dcode = cox.BF16 if dtype == "bf16" else cox.F32
+    k, W, _ = cox.default_cfg(cox.OP_REDUCE if kind == "sum" else cox.OP_DOT, dcode)
+    conv = inputs.bf16_to_f32 if dtype == "bf16" else (lambda a: a)
+    if kind == "sum":
+        exact = oracle_mod.exact_sum(data[0])
+        absum = float(np.abs(conv(data[0]).astype(np.float64)).sum())
+    else:
+        exact = oracle_mod.exact_sum(data[0], data[1])
+        absum = float(np.abs(conv(data[0]).astype(np.float64) * conv(data[1]).astype(np.float64)).sum())
+    nch = -(-N // (32 * W * k))
+    plain_bound, comp_bound = _bounds(k, W, nch, absum, exact)
+    report = {"dtype": dtype, "kind": kind, "n": N, "sigma": [k, W], "cond": absum / abs(exact),
+              "exact": exact}
+    for acc, name, bound in ((cox.PLAIN, "plain", plain_bound), (cox.TWOSUM, "twosum", comp_bound)):
+        print("precision", dtype, kind, name, flush=True)
+        if kind == "sum":
+            t, p = cox.warp_reduce(g[0], acc=acc)
+            op, ot = oracle_mod.reduce(data[0], k, W, acc)
+        else:
+            t, p = cox.warp_dot(g[0], g[1], acc=acc)
+            op, ot = oracle_mod.dot(data[0], data[1], k, W, acc)
+        got = float(down(t)[0])
+        assert np.array_equal(down(p).reshape(-1).view(np.uint32), op.reshape(-1).view(np.uint32))
+        assert np.float64(got).view(np.uint64) == np.float64(ot).view(np.uint64)
+        err = abs(got - exact)
+        assert err <= bound, (name, err, bound)
+        report[name] = {"result": got, "rel_err": err / abs(exact), "rel_bound": bound / abs(exact)}
+    assert report["twosum"]["rel_err"] <= report["plain"]["rel_err"]
+    print("PRECISION " + json.dumps(report), flush=True)
