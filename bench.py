@@ -87,6 +87,75 @@ def cpu_baseline(x, keys, f, sample, sig):
                       f", all five primitives once ({dt:.1f} s wall on {cores} threads)"}
 
 
+def _timed(fn, reps):
+    """Average milliseconds of fn() over reps launches (HIP events on
+    torch's current stream, the stream the binding launches on)."""
+    import torch
+
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def _entry(n, nbytes, ms):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2), "gb_s": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def other_kernels(fg, reps=10):
+    """The kernels outside the timed step, each timed on its own: the
+    block reduce (2^20 int32), the masked warp operations at three
+    densities and the tile reductions (2^26 int32), and the precision
+    variants over 2^28 elements (float32 and bfloat16, sum and dot, plain
+    and TwoSum).  Their timing does not depend on the values, so the
+    precision variants run on the primitive set's float32 N(0, 1) array, a
+    second seeded float32 array and their bfloat16 roundings."""
+    import torch
+
+    from paper_2112_10034_amd import cox, inputs
+
+    res = {}
+    xb = torch.from_numpy(inputs.block_reduce_input()).cuda()
+    nb = xb.numel()
+    bs, wc = cox.warp_reduce_blocks_i32(xb)
+    res["block_reduce_i32_2p20"] = _entry(nb, 4 * nb + 4 * (nb // 256) + 4 * (nb // 32),
+                                          _timed(lambda: cox.warp_reduce_blocks_i32(xb, bs, wc), reps))
+    xm = torch.from_numpy(inputs.masked_input()).cuda()
+    nm = xm.numel()
+    out, rec = torch.empty_like(xm), torch.empty((nm // 32, 4), dtype=torch.int32, device="cuda")
+    for D in inputs.MASK_DENSITIES:
+        res[f"masked_d{D}_2p26"] = _entry(nm, 8 * nm + 16 * (nm // 32),
+                                          _timed(lambda: cox.warp_masked(xm, D, out, rec), reps))
+    for T in inputs.TILE_SIZES:
+        to = torch.empty(nm // T, dtype=torch.int32, device="cuda")
+        res[f"tile_reduce_t{T}_2p26"] = _entry(nm, 4 * nm + 4 * (nm // T),
+                                               _timed(lambda: cox.tile_reduce(xm, T, to), reps))
+    del xm, out, rec
+    n = fg.numel()
+    g2 = torch.Generator(device="cuda")
+    g2.manual_seed(2112100343)
+    f2 = torch.randn(n, dtype=torch.float32, device="cuda", generator=g2)
+    h1, h2 = fg.to(torch.bfloat16), f2.to(torch.bfloat16)
+    tot = torch.empty(1, dtype=torch.float64, device="cuda")
+    for name, a, b, es in (("f32", fg, f2, 4), ("bf16", h1, h2, 2)):
+        for acc, an in ((cox.PLAIN, "plain"), (cox.TWOSUM, "twosum")):
+            res[f"reduce_{name}_{an}_2p28"] = _entry(
+                n, es * n, _timed(lambda: cox.warp_reduce(a, acc=acc, partials=False, total=tot), reps))
+            res[f"dot_{name}_{an}_2p28"] = _entry(
+                n, 2 * es * n, _timed(lambda: cox.warp_dot(a, b, acc=acc, partials=False, total=tot), reps))
+    del f2, h1, h2
+    for ws in cox._ws_cache.values():
+        ws.status()
+    return res
+
+
 def batching(reps=5, base_reps=2):
     """The segmented workload (10,000 lognormal segments): the fused
     reduce + scan + compaction as one autotuned graph-captured launch vs the
@@ -152,6 +221,7 @@ def main():
                     help="elements of each input the oracle runs on (default: the whole batch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the segmented batching comparison")
+    ap.add_argument("--no-others", action="store_true", help="skip the kernels outside the timed step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -296,8 +366,12 @@ def main():
         "roofline": roof,
         "reference": reference,
     }
+    if not args.no_others:
+        log("other kernels")
+        del kg, y, cout, srt
+        out["other_kernels"] = other_kernels(fg)
     if not args.no_batching:
-        del xg, kg, fg, y, cout, srt
+        del xg, fg
         torch.cuda.empty_cache()
         out["batching"] = batching()
     if not args.no_cpu_baseline:

@@ -217,10 +217,14 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
 cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
                          const cox_cfg *cfg, void *stream);
 
-/* thread_block_tile<T> reduction: out[g] = wrap32 sum of x[gT .. gT+T-1]
- * computed with tile.shfl_down(v, o), o = T/2 .. 1, one element per lane;
- * T in {2, 4, 8, 16, 32}; elements past n count as 0.
- * x: int32[n]; out: int32[ceil(n/T)]; device buffers. */
+/* thread_block_tile<T> reduction (static cooperative groups, section
+ * 2.2.2; warp-function support, section 3.2): out[g] = wrap32 sum of
+ * x[gT .. gT+T-1], the value tile.shfl_down(v, o), o = T/2 .. 1, leaves in
+ * the tile's first lane; T in {2, 4, 8, 16, 32}; elements past n count as
+ * 0.  Sums modulo 2^32 do not depend on the order of the additions, so
+ * each lane adds 4 consecutive elements (one 16-byte load) and the T/4
+ * lanes of a tile finish with xor exchanges.  x: int32[n] (4-byte
+ * aligned); out: int32[ceil(n/T)]; device buffers. */
 cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, void *stream);
 
 /* Masked (divergent) warp operations with predicate-derived masks, n % 32

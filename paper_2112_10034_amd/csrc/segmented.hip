@@ -46,11 +46,18 @@ namespace cox {
 
 enum : int { SHDR_NC = 4 };  // header word: total chunk count (setup pass)
 
+// per-chunk descriptor: the chunk's segment and its clamped element range
+struct SegDesc {
+  int64_t a, b;           // segment elements [a, b)
+  uint32_t s, lo, nchs;   // segment, its first chunk, its chunk count
+  uint32_t pad;
+};
+
 struct SegWS {
   uint32_t *hdr;
   uint32_t *chunk_start;  // nseg + 1
   uint32_t *done;         // nseg
-  int32_t *seg_of_chunk;  // maxch
+  SegDesc *desc;          // maxch
   uint64_t *w_scan;       // maxch: look-back words of int chunk sums
   uint64_t *w_cnt;        // maxch: look-back words of kept counts
   uint64_t *w_part;       // maxch: [tag | bits] reduce partials
@@ -71,8 +78,9 @@ static SegWS seg_layout(void *ws, int64_t nseg, int64_t maxch, size_t *bytes) {
   o = align8(o + 4 * (size_t)(nseg + 1));
   w.done = (uint32_t *)(p + o);
   o = align8(o + 4 * (size_t)nseg);
-  w.seg_of_chunk = (int32_t *)(p + o);
-  o = align8(o + 4 * (size_t)maxch);
+  o = (o + 15) & ~(size_t)15;
+  w.desc = (SegDesc *)(p + o);
+  o += sizeof(SegDesc) * (size_t)maxch;
   w.w_scan = (uint64_t *)(p + o);
   o += 8 * (size_t)maxch;
   w.w_cnt = (uint64_t *)(p + o);
@@ -167,14 +175,24 @@ __global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ 
   }
 }
 
-// one logical warp per segment: chunk -> segment map
-__global__ __launch_bounds__(256) void k_seg_map(int64_t nseg, SegWS ws) {
+// one logical warp per segment: the descriptors of its chunks
+__global__ __launch_bounds__(256) void k_seg_map(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
+                                                 SegWS ws) {
   const int64_t wg = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
   const int64_t nw = ((int64_t)gridDim.x * 256) >> 5;
   const int l = threadIdx.x & 31;
   for (int64_t s = wg; s < nseg; s += nw) {
-    const uint32_t a = ws.chunk_start[s], b = ws.chunk_start[s + 1];
-    for (uint32_t c = a + l; c < b; c += 32) ws.seg_of_chunk[c] = (int32_t)s;
+    const uint32_t c0 = ws.chunk_start[s], c1 = ws.chunk_start[s + 1];
+    int64_t a, b;
+    seg_bounds(off, s, n, a, b);
+    SegDesc d;
+    d.a = a;
+    d.b = b;
+    d.s = (uint32_t)s;
+    d.lo = c0;
+    d.nchs = c1 - c0;
+    d.pad = 0u;
+    for (uint32_t c = c0 + l; c < c1; c += 32) ws.desc[c] = d;
   }
 }
 
@@ -219,27 +237,49 @@ __device__ __forceinline__ uint32_t seg_scan32(uint32_t &r, uint32_t &ex) {
   return (uint32_t)bcast31((int)r);
 }
 
-// segment-bounded decoupled look-back (warp 0): chunks below `lo` count as
-// an inclusive prefix of 0
-__device__ uint32_t seg_lookback(int64_t c, int64_t lo, uint32_t agg, uint64_t *__restrict__ st, uint32_t tag,
-                                 uint32_t *__restrict__ hdr) {
+// Segment-bounded decoupled look-back, run by the 32 lanes of one logical
+// warp in two halves so that the block's prefetch can be issued in
+// between.  seg_lb_begin publishes the chunk's aggregate (an inclusive
+// prefix at the segment's first chunk lo) and requests the first window of
+// predecessor words (lane l: chunk c - 1 - l; chunks below lo count as the
+// inclusive prefix 0); seg_lb_end waits for them, walks back 32 chunks at
+// a time until a lane finds an inclusive prefix, and publishes the chunk's
+// own.  Returns the exclusive prefix (same in every lane).
+__device__ __forceinline__ uint64_t seg_lb_begin(int64_t c, int64_t lo, uint32_t agg, uint64_t *__restrict__ st,
+                                                 uint32_t tag) {
   const int l = llane();
   if (c == lo) {
     if (l == 0) st_dev(&st[c], st_pack(tag, ST_PREFIX, agg));
-    return 0u;
+    return 0;
   }
   if (l == 0) st_dev(&st[c], st_pack(tag, ST_AGG, agg));
+  const int64_t idx = c - 1 - l;
+  return idx >= lo ? ld_dev(&st[idx]) : st_pack(tag, ST_PREFIX, 0u);
+}
+
+__device__ __forceinline__ uint32_t seg_wsum(uint32_t v) {
+  v += (uint32_t)xor_lane<16>((int)v);
+  v += (uint32_t)xor_lane<8>((int)v);
+  v += (uint32_t)xor_lane<4>((int)v);
+  v += (uint32_t)xor_lane<2>((int)v);
+  v += (uint32_t)xor_lane<1>((int)v);
+  return v;
+}
+
+__device__ uint32_t seg_lb_end(int64_t c, int64_t lo, uint32_t agg, uint64_t first, uint64_t *__restrict__ st,
+                               uint32_t tag, uint32_t *__restrict__ hdr) {
+  const int l = llane();
+  if (c == lo) return 0u;
   uint32_t run = 0u;
   int64_t top = c - 1;
+  uint64_t s = first;
   for (;;) {
     const int64_t idx = top - l;
-    uint64_t s = st_pack(tag, ST_PREFIX, 0u);
     if (idx >= lo) {
-      s = ld_dev(&st[idx]);
       uint32_t spins = 0;
       while (st_tag(s) != tag || st_flag(s) == 0u) {
         if (++spins >= MAX_SPIN || ((spins & 1023u) == 0u && ld_dev32(&hdr[HDR_ERR]) == tag)) {
-          st_dev32(&hdr[HDR_ERR], tag);
+          st_dev32(&hdr[HDR_ERR], tag);  // give up: result invalid, kernel still ends
           break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -247,32 +287,20 @@ __device__ uint32_t seg_lookback(int64_t c, int64_t lo, uint32_t agg, uint64_t *
       }
     }
     const uint32_t pm = ballot(st_flag(s) == ST_PREFIX);
-    uint32_t v = st_val(s);
     if (pm) {
       const int p = __builtin_ctz(pm);
-      v = l <= p ? v : 0u;
-      v += (uint32_t)xor_lane<16>((int)v);
-      v += (uint32_t)xor_lane<8>((int)v);
-      v += (uint32_t)xor_lane<4>((int)v);
-      v += (uint32_t)xor_lane<2>((int)v);
-      v += (uint32_t)xor_lane<1>((int)v);
-      run += v;
+      run += seg_wsum(l <= p ? st_val(s) : 0u);
       break;
     }
-    v += (uint32_t)xor_lane<16>((int)v);
-    v += (uint32_t)xor_lane<8>((int)v);
-    v += (uint32_t)xor_lane<4>((int)v);
-    v += (uint32_t)xor_lane<2>((int)v);
-    v += (uint32_t)xor_lane<1>((int)v);
-    run += v;
+    run += seg_wsum(st_val(s));
     top -= 32;
+    s = top - l >= lo ? ld_dev(&st[top - l]) : st_pack(tag, ST_PREFIX, 0u);
   }
   if (l == 0) st_dev(&st[c], st_pack(tag, ST_PREFIX, agg + run));
   return run;
 }
 
-// value bits of tagged word p[i] for i in [a, b) (lanes of warp 0 fetch 32
-// at a time); `fold` is applied in index order by lane 0's loop
+// value bits of tagged word p[i] (bounded wait for the call's tag)
 __device__ __forceinline__ uint64_t seg_word(const uint64_t *p, int64_t i, uint32_t tag, uint32_t *hdr) {
   uint64_t s = ld_dev(&p[i]);
   uint32_t spins = 0;
@@ -288,7 +316,7 @@ __device__ __forceinline__ uint64_t seg_word(const uint64_t *p, int64_t i, uint3
 }
 
 // FP64 serial sum from -0.0 of the float bits in words [a, b), in index
-// order (warp 0; same value in every lane)
+// order (one logical warp; same value in every lane)
 __device__ double seg_serial_f64(const uint64_t *p, int64_t a, int64_t b, uint32_t tag, uint32_t *hdr) {
   const int l = llane();
   double acc = -0.0;
@@ -302,12 +330,30 @@ __device__ double seg_serial_f64(const uint64_t *p, int64_t a, int64_t b, uint32
   return acc;
 }
 
-// float scan carry of chunk c (warp 0): the FP64 sum from -0.0, in chunk
-// order, of the totals T of chunks lo..c-1, taken from the nearest earlier
-// chunk that has published its inclusive prefix; then publishes this
-// chunk's inclusive prefix carry + T_c.  The window is the 32 chunks below
-// c, re-read until one of them (or the segment start) has a prefix.
-__device__ double seg_lookback_f64(int64_t c, int64_t lo, uint32_t tc, const SegWS &ws, uint32_t tag) {
+// Float scan carry of chunk c: the FP64 sum from -0.0, in chunk order, of
+// the totals T of chunks lo..c-1.  A serial sum continues exactly from any
+// of its prefixes, so the carry starts from the nearest earlier chunk that
+// has published its inclusive prefix (two tagged 32-bit halves) and adds
+// the totals after it in order.  The window is the 32 chunks below c,
+// re-read until one of them (or the segment start, as the prefix -0.0) has
+// a prefix.  seg_f64_begin requests the window, seg_f64_end resolves it and
+// publishes this chunk's inclusive prefix carry + T_c.
+struct F64Win {
+  uint64_t h, lw, t;
+};
+
+__device__ __forceinline__ F64Win seg_f64_begin(int64_t c, int64_t lo, const SegWS &ws) {
+  F64Win r = {0, 0, 0};
+  const int64_t idx = c - 1 - llane();
+  if (c > lo && idx >= lo) {
+    r.h = ld_dev(&ws.w_ph[idx]);
+    r.lw = ld_dev(&ws.w_pl[idx]);
+    r.t = ld_dev(&ws.w_tot[idx]);
+  }
+  return r;
+}
+
+__device__ double seg_f64_end(int64_t c, int64_t lo, uint32_t tc, F64Win win, const SegWS &ws, uint32_t tag) {
   const int l = llane();
   double carry = -0.0;
   if (c > lo) {
@@ -318,12 +364,21 @@ __device__ double seg_lookback_f64(int64_t c, int64_t lo, uint32_t tc, const Seg
       double pv = -0.0;
       float tv = -0.0f;
       if (!pref) {
-        const uint64_t h = ld_dev(&ws.w_ph[idx]), lw = ld_dev(&ws.w_pl[idx]);
-        if ((uint32_t)(h >> 32) == tag && (uint32_t)(lw >> 32) == tag) {
+        if ((uint32_t)(win.h >> 32) == tag && (uint32_t)(win.lw >> 32) == tag) {
           pref = true;
-          pv = __hiloint2double((int)(uint32_t)h, (int)(uint32_t)lw);
+          pv = __hiloint2double((int)(uint32_t)win.h, (int)(uint32_t)win.lw);
         } else {
-          tv = i2f((int)(uint32_t)seg_word(ws.w_tot, idx, tag, ws.hdr));
+          // totals are published before their chunk's own look-back
+          uint32_t ts = 0;
+          while ((uint32_t)(win.t >> 32) != tag) {
+            if (++ts >= MAX_SPIN || ((ts & 1023u) == 0u && ld_dev32(&ws.hdr[HDR_ERR]) == tag)) {
+              st_dev32(&ws.hdr[HDR_ERR], tag);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            win.t = ld_dev(&ws.w_tot[idx]);
+          }
+          tv = i2f((int)(uint32_t)win.t);
         }
       }
       const uint32_t pm = ballot(pref);
@@ -339,6 +394,10 @@ __device__ double seg_lookback_f64(int64_t c, int64_t lo, uint32_t tc, const Seg
         break;
       }
       __builtin_amdgcn_s_sleep(1);
+      if (idx >= lo) {
+        win.h = ld_dev(&ws.w_ph[idx]);
+        win.lw = ld_dev(&ws.w_pl[idx]);
+      }
     }
   }
   const double pc = carry + (double)i2f((int)tc);
@@ -349,7 +408,7 @@ __device__ double seg_lookback_f64(int64_t c, int64_t lo, uint32_t tc, const Seg
   return carry;
 }
 
-// int64 sum of the int32 bits in words [a, b) (warp 0)
+// int64 sum of the int32 bits in words [a, b) (one logical warp)
 __device__ long long seg_sum_i64(const uint64_t *p, int64_t a, int64_t b, uint32_t tag, uint32_t *hdr) {
   const int l = llane();
   long long acc = 0;
@@ -358,7 +417,21 @@ __device__ long long seg_sum_i64(const uint64_t *p, int64_t a, int64_t b, uint32
   return acc;
 }
 
+// 16-byte vectors at 4-byte aligned addresses (segments start anywhere):
+// one dwordx4 access each, which gfx950 serves without alignment faults
+typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2u __attribute__((ext_vector_type(2), aligned(4)));
+
 // ---------------------------------------------------------------- fused kernel
+// Per block: draw a ticket and resolve it, with one dependent load, into
+// one of two shared descriptor slots; for each chunk: (1) one thread of the
+// block's last wave draws and resolves the next ticket while the block
+// loads the chunk and does its row work (reduce partials, compaction ranks
+// staged in the warp's LDS region, scan rows); (2) role warps on different
+// waves combine the warp values, publish them and run their look-backs --
+// scan on warp 0, compaction on warp 2, reduce total on warp 4 (folded onto
+// warp 0 in small blocks); a segment of one chunk needs no cross-block
+// word at all; (3) outputs.
 template <int K, int DT>
 __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__ x, const int64_t *__restrict__ off,
                                                     int64_t nseg, int64_t n, int64_t nc_arg, SegWS ws,
@@ -367,8 +440,9 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   constexpr int V = K < 4 ? K : 4;
   constexpr int R = K / V;
   using T = SegT<DT>;
-  __shared__ uint32_t s_epoch, s_ticket, s_seg, s_nchs;
-  __shared__ int64_t s_e0, s_e1, s_lo, s_obase;
+  __shared__ uint32_t s_epoch;
+  __shared__ uint32_t s_tk[2], s_seg[2], s_lo[2], s_nchs[2];
+  __shared__ int64_t s_e0[2], s_e1[2], s_ob[2];
   __shared__ uint32_t s_wred[32], s_wscan[32], s_wcnt[32], s_E[32], s_coff[32];
   __shared__ uint32_t s_last[3];
   __shared__ uint32_t s_pre_i, s_pre_c;
@@ -377,58 +451,56 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
 
   const int W = blockDim.x >> 5;
   const int w = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int wS = 0, wC = W > 2 ? 2 : 0, wR = W > 4 ? 4 : 0;
+  const int tD = blockDim.x >= 128 ? (int)blockDim.x - 64 : 0;  // draws tickets
   const int64_t S = (int64_t)blockDim.x * K;
   const uint32_t lt = lanemask_lt();
-  if (threadIdx.x == 0) s_epoch = ld_epoch(ws.hdr);
-  __syncthreads();
-  const uint32_t epoch = s_epoch;
-  const uint32_t tag = tag_of_epoch(epoch);
-  const int64_t NC = nc_arg >= 0 ? nc_arg : (int64_t)ld_dev32(&ws.hdr[SHDR_NC]);
+  const bool single = nc_arg >= 0;
+  const int64_t NC = single ? nc_arg : (int64_t)ld_dev32(&ws.hdr[SHDR_NC]);
 
-  for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t t = add_dev32(&ws.hdr[HDR_TICKET], 1u);
-      s_ticket = t;
-      if ((int64_t)t < NC) {
-        const int64_t s = nc_arg >= 0 ? 0 : ws.seg_of_chunk[t];
-        const int64_t lo = nc_arg >= 0 ? 0 : ws.chunk_start[s];
-        const int64_t nchs = nc_arg >= 0 ? nc_arg : (int64_t)ws.chunk_start[s + 1] - lo;
-        int64_t a, b;
-        seg_bounds(off, s, n, a, b);
-        s_seg = (uint32_t)s;
-        s_lo = lo;
-        s_nchs = (uint32_t)nchs;
-        s_obase = a;
-        s_e0 = a + ((int64_t)t - lo) * S;
-        s_e1 = b;
+  // thread tD: ticket t's chunk into slot
+  auto resolve = [&](uint32_t t, int slot) {
+    s_tk[slot] = t;
+    if ((int64_t)t < NC) {
+      int64_t a, b, s, lo, nchs;
+      if (single) {
+        seg_bounds(off, 0, n, a, b);
+        s = 0;
+        lo = 0;
+        nchs = nc_arg;
+      } else {
+        const SegDesc d = ws.desc[t];
+        a = d.a;
+        b = d.b;
+        s = d.s;
+        lo = d.lo;
+        nchs = d.nchs;
       }
+      s_seg[slot] = (uint32_t)s;
+      s_lo[slot] = (uint32_t)lo;
+      s_nchs[slot] = (uint32_t)nchs;
+      s_ob[slot] = a;
+      s_e0[slot] = a + ((int64_t)t - lo) * S;
+      s_e1[slot] = b;
     }
-    __syncthreads();
-    const int64_t c = s_ticket;
-    if (c >= NC) break;
-    const int64_t s = s_seg, lo = s_lo, e0 = s_e0, e1 = s_e1;
-    const uint32_t nchs = s_nchs;
-
-    // ---- load (padding with the identity)
-    uint32_t xr[R][V];
+  };
+  // the chunk's vectors (padding with the identity past the segment)
+  auto load = [&](int64_t e0, int64_t e1, uint32_t (&v)[R][V]) {
     const int64_t wbase = e0 + (int64_t)w * 32 * K;
-    if (e0 + S <= e1 && V == 4 && (e0 & 3) == 0) {
-      // 16-byte aligned chunk: one vector per row
+    if (e0 + S <= e1) {
+      const uint32_t *src = x + wbase + l * V;
 #pragma unroll
       for (int i = 0; i < R; i++) {
-        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
-        const u32x4 q = ld_stream4(x + e);
-        xr[i][0] = q[0];
-#pragma unroll
-        for (int j = 1; j < V; j++) xr[i][j] = q[j];
-      }
-    } else if (e0 + S <= e1) {
-      // segments start anywhere: element loads
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
-#pragma unroll
-        for (int j = 0; j < V; j++) xr[i][j] = ld_stream1(x + e + j);
+        const uint32_t *p = src + i * 32 * V;
+        if constexpr (V == 4) {
+          const u32x4u q = __builtin_nontemporal_load((const u32x4u *)p);
+          v[i][0] = q.x; v[i][1] = q.y; v[i][2] = q.z; v[i][3] = q.w;
+        } else if constexpr (V == 2) {
+          const u32x2u q = __builtin_nontemporal_load((const u32x2u *)p);
+          v[i][0] = q.x; v[i][1] = q.y;
+        } else {
+          v[i][0] = ld_stream1(p);
+        }
       }
     } else {
 #pragma unroll
@@ -436,9 +508,34 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
 #pragma unroll
         for (int j = 0; j < V; j++) {
           const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-          xr[i][j] = e < e1 ? ld_stream1(x + e) : T::ident;
+          v[i][j] = e < e1 ? ld_stream1(x + e) : T::ident;
         }
     }
+  };
+
+  if (threadIdx.x == 0) s_epoch = ld_epoch(ws.hdr);
+  __syncthreads();
+  const uint32_t epoch = s_epoch;
+  const uint32_t tag = tag_of_epoch(epoch);
+  const int slot = 0;
+
+  int64_t c;
+  for (;;) {
+    // a ticket is drawn only when the block can start on it at once: a
+    // drawn chunk that waited for the block's previous one would hold up
+    // the look-backs of the chunks after it
+    if (threadIdx.x == tD) resolve(add_dev32(&ws.hdr[HDR_TICKET], 1u), 0);
+    __syncthreads();
+    c = s_tk[0];
+    if (c >= NC) break;
+    // the slot is read here only: the next ticket overwrites it while slow
+    // threads may still be writing this chunk's outputs
+    const int64_t s = s_seg[slot], lo = s_lo[slot], e0 = s_e0[slot], e1 = s_e1[slot], ob = s_ob[slot];
+    const uint32_t nchs = s_nchs[slot];
+    const bool full = e0 + S <= e1;
+    const int64_t wbase = e0 + (int64_t)w * 32 * K;
+    uint32_t xr[R][V];
+    load(e0, e1, xr);
 
     // ---- reduce partial: lane-serial then the warp tree
     if (flags & SF_REDUCE) {
@@ -450,28 +547,8 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
       a = seg_tree<DT>(a);
       if (l == 0) s_wred[w] = a;
     }
-    // ---- chunk-local scan
-    uint32_t z[R][V], exv[R], cin[R];
-    if (flags & SF_SCAN) {
-      uint32_t carry = T::ident;
-#pragma unroll
-      for (int i = 0; i < R; i++) {
-        z[i][0] = xr[i][0];
-#pragma unroll
-        for (int j = 1; j < V; j++) z[i][j] = T::add(z[i][j - 1], xr[i][j]);
-        uint32_t r = z[i][V - 1];
-        const uint32_t rt = seg_scan32<DT>(r, exv[i]);
-        cin[i] = carry;
-        carry = T::add(carry, rt);
-      }
-      if (l == 0) s_wscan[w] = carry;
-      if (w == W - 1 && l == 31) {
-        s_last[0] = cin[R - 1];
-        s_last[1] = exv[R - 1];
-        s_last[2] = z[R - 1][V - 1];
-      }
-    }
-    // ---- compaction ranks, staged in the warp's LDS region
+    // ---- compaction ranks, staged in the warp's LDS region (before the
+    // scan rewrites the row registers)
     if (flags & SF_COMPACT) {
       uint32_t *region = s_stage + w * 32 * K;
       uint32_t run = 0u;
@@ -494,60 +571,45 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
       }
       if (l == 0) s_wcnt[w] = run;
     }
+    // ---- chunk-local scan (in place: xr becomes the lane prefixes z)
+    uint32_t exv[R], cin[R];
+    if (flags & SF_SCAN) {
+      uint32_t carry = T::ident;
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+#pragma unroll
+        for (int j = 1; j < V; j++) xr[i][j] = T::add(xr[i][j - 1], xr[i][j]);
+        uint32_t r = xr[i][V - 1];
+        const uint32_t rt = seg_scan32<DT>(r, exv[i]);
+        cin[i] = carry;
+        carry = T::add(carry, rt);
+      }
+      if (l == 0) s_wscan[w] = carry;
+      if (w == W - 1 && l == 31) {
+        s_last[0] = cin[R - 1];
+        s_last[1] = exv[R - 1];
+        s_last[2] = xr[R - 1][V - 1];
+      }
+    }
     __syncthreads();
+    const bool one = nchs == 1;  // the segment is this chunk alone
 
-    // ---- warp 0: block combines, publication, look-backs, totals
-    if (w == 0) {
-      uint32_t agg_s = 0u, agg_c = 0u;
-      if (flags & SF_REDUCE) {
-        uint32_t b = l < W ? s_wred[l] : T::ident;
-        b = seg_tree<DT>(b);
-        if (l == 0) st_dev(&ws.w_part[c], ((uint64_t)tag << 32) | b);
-      }
-      if (flags & SF_SCAN) {
-        uint32_t a = l < W ? s_wscan[l] : T::ident;
-        uint32_t ex;
-        const uint32_t tot = seg_scan32<DT>(a, ex);
-        s_E[l] = ex;  // lanes >= W are not read
-        if constexpr (DT == COX_I32) {
-          agg_s = tot;
-        } else {
-          // q at the chunk's last slot: ((E_{W-1} + C) + ex) + z
-          const uint32_t ew = (uint32_t)shfl((int)ex, W - 1);
-          agg_s = T::add(T::add(T::add(ew, s_last[0]), s_last[1]), s_last[2]);
-          if (l == 0) st_dev(&ws.w_tot[c], ((uint64_t)tag << 32) | agg_s);
+    // ---- roles
+    if ((flags & SF_REDUCE) && w == wR) {
+      uint32_t b = l < W ? s_wred[l] : T::ident;
+      b = seg_tree<DT>(b);
+      if (one) {
+        if (l == 0) {
+          if constexpr (DT == COX_I32) ((long long *)seg_total)[s] = (long long)(int32_t)b;
+          else ((double *)seg_total)[s] = -0.0 + (double)i2f((int)b);
         }
-      }
-      if (flags & SF_COMPACT) {
-        const uint32_t a = l < W ? s_wcnt[l] : 0u;
-        uint32_t incl = a;
-        incl += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)incl);
-        incl += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)incl);
-        incl += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)incl);
-        incl += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)incl);
-        incl += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)incl);
-        s_coff[l] = incl - a;
-        agg_c = (uint32_t)bcast31((int)incl);
-      }
-      // look-backs inside the segment
-      if (flags & SF_SCAN) {
-        if constexpr (DT == COX_I32) {
-          const uint32_t pre = seg_lookback(c, lo, agg_s, ws.w_scan, tag, ws.hdr);
-          if (l == 0) s_pre_i = pre;
-        } else {
-          const double pre = seg_lookback_f64(c, lo, agg_s, ws, tag);
-          if (l == 0) s_pre_f = pre;
-        }
-      }
-      if (flags & SF_COMPACT) {
-        const uint32_t pre = seg_lookback(c, lo, agg_c, ws.w_cnt, tag, ws.hdr);
-        if (l == 0) s_pre_c = pre;
-        if (seg_count && c == lo + nchs - 1 && l == 0) seg_count[s] = (long long)pre + (long long)agg_c;
-      }
-      // segment total by the chunk that completes the segment's count
-      if (flags & SF_REDUCE) {
+      } else {
         uint32_t d = 0u;
-        if (l == 0) d = add_dev32(&ws.done[s], 1u);
+        if (l == 0) {
+          st_dev(&ws.w_part[c], ((uint64_t)tag << 32) | b);
+          d = add_dev32(&ws.done[s], 1u);
+        }
+        // the chunk completing the segment's count adds its partials
         d = (uint32_t)__shfl((int)d, 0, 32);
         if (d == nchs - 1) {
           if constexpr (DT == COX_I32) {
@@ -561,21 +623,57 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
         }
       }
     }
+    if ((flags & SF_SCAN) && w == wS) {
+      uint32_t a = l < W ? s_wscan[l] : T::ident;
+      uint32_t ex;
+      const uint32_t tot = seg_scan32<DT>(a, ex);
+      s_E[l] = ex;  // lanes >= W are not read
+      if constexpr (DT == COX_I32) {
+        uint32_t pre = 0u;
+        if (!one) pre = seg_lb_end(c, lo, tot, seg_lb_begin(c, lo, tot, ws.w_scan, tag), ws.w_scan, tag, ws.hdr);
+        if (l == 0) s_pre_i = pre;
+      } else {
+        double pre = -0.0;
+        if (!one) {
+          // q at the chunk's last slot: ((E_{W-1} + C) + ex) + z
+          const uint32_t ew = (uint32_t)shfl((int)ex, W - 1);
+          const uint32_t tc = T::add(T::add(T::add(ew, s_last[0]), s_last[1]), s_last[2]);
+          if (l == 0) st_dev(&ws.w_tot[c], ((uint64_t)tag << 32) | tc);
+          pre = seg_f64_end(c, lo, tc, seg_f64_begin(c, lo, ws), ws, tag);
+        }
+        if (l == 0) s_pre_f = pre;
+      }
+    }
+    if ((flags & SF_COMPACT) && w == wC) {
+      const uint32_t a = l < W ? s_wcnt[l] : 0u;
+      uint32_t incl = a;
+      incl += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)incl);
+      incl += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)incl);
+      incl += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)incl);
+      incl += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)incl);
+      incl += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)incl);
+      s_coff[l] = incl - a;
+      const uint32_t agg = (uint32_t)bcast31((int)incl);
+      uint32_t pre = 0u;
+      if (!one) pre = seg_lb_end(c, lo, agg, seg_lb_begin(c, lo, agg, ws.w_cnt, tag), ws.w_cnt, tag, ws.hdr);
+      if (l == 0) {
+        s_pre_c = pre;
+        if (seg_count && c == lo + nchs - 1) seg_count[s] = (long long)pre + (long long)agg;
+      }
+    }
     __syncthreads();
 
     // ---- outputs
     if (flags & SF_SCAN) {
       const uint32_t E = w == 0 ? T::ident : s_E[w];
+      uint32_t o[R][V];
       if constexpr (DT == COX_I32) {
         const uint32_t pre = s_pre_i;
 #pragma unroll
         for (int i = 0; i < R; i++) {
           const uint32_t base = T::add(T::add(E, cin[i]), exv[i]);
 #pragma unroll
-          for (int j = 0; j < V; j++) {
-            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-            if (e < e1) y[e] = pre + T::add(base, z[i][j]);
-          }
+          for (int j = 0; j < V; j++) o[i][j] = pre + T::add(base, xr[i][j]);
         }
       } else {
         const double pre = s_pre_f;
@@ -584,39 +682,58 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
           const uint32_t base = T::add(T::add(E, cin[i]), exv[i]);
 #pragma unroll
           for (int j = 0; j < V; j++) {
-            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-            const float q = i2f((int)T::add(base, z[i][j]));
-            if (e < e1) y[e] = (uint32_t)f2i((float)(pre + (double)q));
+            const float q = i2f((int)T::add(base, xr[i][j]));
+            o[i][j] = (uint32_t)f2i((float)(pre + (double)q));
           }
         }
+      }
+      if (full && V == 4) {
+        uint32_t *dst = y + wbase + l * V;
+        if ((e0 & 3) == 0) {
+#pragma unroll
+          for (int i = 0; i < R; i++) st_stream4(dst + i * 32 * V, o[i][0], o[i][V > 1 ? 1 : 0],
+                                                 o[i][V > 2 ? 2 : 0], o[i][V > 3 ? 3 : 0]);
+        } else {
+          // plain stores: L2 joins the warps' unaligned runs into lines
+#pragma unroll
+          for (int i = 0; i < R; i++) {
+            const u32x4u q = {o[i][0], o[i][V > 1 ? 1 : 0], o[i][V > 2 ? 2 : 0], o[i][V > 3 ? 3 : 0]};
+            *(u32x4u *)(dst + i * 32 * V) = q;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < R; i++)
+#pragma unroll
+          for (int j = 0; j < V; j++) {
+            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
+            if (e < e1) y[e] = o[i][j];
+          }
       }
     }
     if (flags & SF_COMPACT) {
       const uint32_t *region = s_stage + w * 32 * K;
       const uint32_t wcnt = s_wcnt[w];
-      const int64_t obase = s_obase + (int64_t)s_pre_c + s_coff[w];
+      const int64_t obase = ob + (int64_t)s_pre_c + s_coff[w];
       for (uint32_t q = l; q < wcnt; q += 32) {
         const int64_t pos = obase + q;
         if (pos < e1) outc[pos] = region[q];  // bound: guards a failed wait only
       }
     }
-    __syncthreads();  // LDS reuse by the next chunk
   }
 
-  if (threadIdx.x == 0) {
-    const uint32_t t = s_ticket;
-    if (t == (uint32_t)(NC + gridDim.x - 1)) {
+  if (threadIdx.x == tD && c == NC + (int64_t)gridDim.x - 1) {
+    // last exit ticket (every block has drawn its last one)
+    if (nc_arg == 0) {
       // single-segment launch of an empty segment: identity outputs
-      if (nc_arg == 0) {
-        if ((flags & SF_REDUCE) && seg_total) {
-          if (DT == COX_I32) ((long long *)seg_total)[0] = 0;
-          else ((double *)seg_total)[0] = -0.0;
-        }
-        if ((flags & SF_COMPACT) && seg_count) seg_count[0] = 0;
+      if ((flags & SF_REDUCE) && seg_total) {
+        if (DT == COX_I32) ((long long *)seg_total)[0] = 0;
+        else ((double *)seg_total)[0] = -0.0;
       }
-      st_dev32(&ws.hdr[HDR_TICKET], 0u);
-      st_dev32(&ws.hdr[HDR_EPOCH], epoch + 1u);
+      if ((flags & SF_COMPACT) && seg_count) seg_count[0] = 0;
     }
+    st_dev32(&ws.hdr[HDR_TICKET], 0u);
+    st_dev32(&ws.hdr[HDR_EPOCH], epoch + 1u);
   }
 }
 
@@ -718,7 +835,7 @@ static cox_status seg_launch(const SegCall &sc, hipStream_t st) {
   if (r != COX_OK) return r;
   int mg = (int)((sc.nseg * 32 + 255) / 256);
   if (mg > 4096) mg = 4096;
-  hipLaunchKernelGGL(k_seg_map, dim3(mg), dim3(256), 0, st, sc.nseg, sc.ws);
+  hipLaunchKernelGGL(k_seg_map, dim3(mg), dim3(256), 0, st, sc.off, sc.nseg, sc.n, sc.ws);
   r = launch_status();
   if (r != COX_OK) return r;
   hipLaunchKernelGGL(sc.fn, dim3(sc.grid), dim3(block), sc.lds, st, (const uint32_t *)sc.x, sc.off, sc.nseg, sc.n,

@@ -1,91 +1,159 @@
 // thread_block_tile<T> reductions and masked (divergent) warp operations.
 //
-// Both kernels keep CUDA's one-element-per-lane mapping: element e sits in
-// logical lane e & 31 of logical warp e >> 5.  A block handles R rows of 256
+// Masked operations keep CUDA's one-element-per-lane mapping: element e
+// sits in logical lane e & 31 of logical warp e >> 5, since the masks are
+// built from per-lane predicates.  A block handles R rows of 256
 // consecutive elements per round (coalesced streaming 4-byte loads, R loads
 // in flight per thread), and the whole block runs every round so that the
-// fixed-pattern exchanges always see full warps.  The default grid is four
+// exchanges always see full warps.
+//
+// Tile reductions are int32 sums modulo 2^32, whose value does not depend
+// on the order of the additions, so the kernel loads 16-byte vectors: a
+// lane holds 4 consecutive elements, adds them, and a tile of T elements is
+// finished by the xor exchanges of the T/4 lanes holding it -- the same bits
+// as the one-element-per-lane shfl_down tree.  The default grid is four
 // 256-thread blocks per compute unit.
 #include "cox_internal.hpp"
 
 namespace cox {
 
+// 16-byte vectors at 4-byte aligned addresses (one dwordx4 access each)
+typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
+// the lanes of a tile hold T/4 x 4 consecutive elements: in-lane sum, then
+// xor exchanges inside the T/4-lane group (its first lane ends with the sum)
 template <int T>
-__device__ __forceinline__ uint32_t tile_tree(uint32_t v) {
-  // tile.shfl_down(v, o) for o = T/2 .. 1; the tile's first lane only reads
-  // lanes of its own tile, where the xor partner l ^ o equals l + o
-  if constexpr (T >= 32) v += (uint32_t)xor_lane<16>((int)v);
-  if constexpr (T >= 16) v += (uint32_t)xor_lane<8>((int)v);
-  if constexpr (T >= 8) v += (uint32_t)xor_lane<4>((int)v);
-  if constexpr (T >= 4) v += (uint32_t)xor_lane<2>((int)v);
-  if constexpr (T >= 2) v += (uint32_t)xor_lane<1>((int)v);
-  return v;
+__device__ __forceinline__ void tile_sums(const uint32_t (&v)[4], uint32_t &a, uint32_t &b) {
+  if constexpr (T == 2) {
+    a = v[0] + v[1];
+    b = v[2] + v[3];
+  } else {
+    uint32_t s = (v[0] + v[1]) + (v[2] + v[3]);
+    if constexpr (T >= 8) s += (uint32_t)xor_lane<1>((int)s);
+    if constexpr (T >= 16) s += (uint32_t)xor_lane<2>((int)s);
+    if constexpr (T >= 32) s += (uint32_t)xor_lane<4>((int)s);
+    a = s;
+    b = 0u;
+  }
 }
 
 template <int T, int R>
 __global__ __launch_bounds__(256) void k_tile_reduce(const int32_t *__restrict__ x, int64_t n,
                                                      int32_t *__restrict__ out) {
+  constexpr int G = T >= 4 ? T / 4 : 1;  // lanes per tile
   const int t = threadIdx.x, l = t & 31;
-  const int64_t per_block = 256 * R;
+  const int64_t per_block = 1024 * R;
   const int64_t stride = (int64_t)gridDim.x * per_block;
   const int64_t rounds = (n + stride - 1) / stride;
+  const int64_t nt = (n + T - 1) / T;
   for (int64_t it = 0; it < rounds; it++) {
     const int64_t base = it * stride + (int64_t)blockIdx.x * per_block;
-    uint32_t v[R];
+    uint32_t v[R][4];
+    if (base + per_block <= n) {
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-      const int64_t e = base + r * 256 + t;
-      v[r] = e < n ? ld_stream1(x + e) : 0u;
+      for (int r = 0; r < R; r++) {
+        const u32x4u q = __builtin_nontemporal_load((const u32x4u *)(x + base + r * 1024 + 4 * t));
+        v[r][0] = q.x; v[r][1] = q.y; v[r][2] = q.z; v[r][3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int64_t e = base + r * 1024 + 4 * t + j;
+          v[r][j] = e < n ? ld_stream1(x + e) : 0u;
+        }
     }
 #pragma unroll
     for (int r = 0; r < R; r++) {
-      const int64_t e = base + r * 256 + t;
-      const uint32_t s = tile_tree<T>(v[r]);
-      if ((l & (T - 1)) == 0 && e < n) out[e / T] = (int32_t)s;
+      const int64_t e = base + r * 1024 + 4 * t;  // first element of the lane
+      uint32_t a, b;
+      tile_sums<T>(v[r], a, b);
+      if constexpr (T == 2) {
+        if (e / 2 < nt) out[e / 2] = (int32_t)a;
+        if (e / 2 + 1 < nt) out[e / 2 + 1] = (int32_t)b;
+      } else {
+        if ((l & (G - 1)) == 0 && e / T < nt) out[e / T] = (int32_t)a;
+      }
     }
   }
 }
 
+// The masked operations without a divergent branch: every ballot is taken
+// once over the whole wave (a wave-uniform 64-bit value in scalar
+// registers), each logical warp's mask m, its ballot b, any / all results
+// and leader broadcast are derived from the half of that value, and every
+// lane computes its shuffle; lanes outside m then store INT32_MIN instead.
+// The stored values are those of the divergent CUDA code, whose lanes of m
+// are exactly the lanes that would execute it.  The warp's record is
+// written by its logical lane 0 (same bytes as writing it from the leader).
 template <int R>
 __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__ x, int64_t n, int D,
                                                      int32_t *__restrict__ out, uint32_t *__restrict__ rec) {
   const int t = threadIdx.x, l = t & 31;
+  const bool hi = (t & 32) != 0;
   const int64_t per_block = 256 * R;
   const int64_t stride = (int64_t)gridDim.x * per_block;
   const int64_t rounds = (n + stride - 1) / stride;
+  // lanes of m above l: m & ~(2^(l+1) - 1)
+  const uint32_t above_mask = l == 31 ? 0u : (FULL << (l + 1));
   for (int64_t it = 0; it < rounds; it++) {
     const int64_t base = it * stride + (int64_t)blockIdx.x * per_block;
-    int32_t xs[R];
+    if (base + per_block <= n) {
+      const int32_t *src = x + base + t;
+      int32_t *dst = out + base + t;
+      uint32_t *rdst = rec + 4 * ((base + t) >> 5);
+      int32_t xs[R];
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-      const int64_t e = base + r * 256 + t;
-      xs[r] = e < n ? (int32_t)ld_stream1(x + e) : 0;
-    }
+      for (int r = 0; r < R; r++) xs[r] = (int32_t)ld_stream1(src + r * 256);
 #pragma unroll
-    for (int r = 0; r < R; r++) {
-      const int64_t e = base + r * 256 + t;
-      if (e >= n) continue;  // whole logical warps (n % 32 == 0)
-      const int32_t xv = xs[r];
-      const int64_t g = e >> 5;
-      const bool p = ((uint32_t)xv & 1023u) < (uint32_t)D;
-      const uint32_t m = ballot(p);
-      if (p) {
-        // divergent region: exactly the lanes of m execute
-        const uint32_t b = ballot_sync(m, xv > 0);
-        const bool A = any_sync(m, ((xv >> 10) & 31) == 0);
-        const bool L = all_sync(m, ((xv >> 15) & 31) != 0);
-        const uint32_t above = l == 31 ? 0u : (m & (FULL << (l + 1)));
-        const int src = above ? __builtin_ctz(above) : __builtin_ctz(m);
-        const int ld = __builtin_ctz(m);
-        const int32_t s = shfl(xv, src);
-        const int32_t bc = shfl(xv, ld);
-        out[e] = s;
-        if (l == ld)
-          *(uint4 *)(rec + 4 * g) = make_uint4(m, b, (uint32_t)A | ((uint32_t)L << 1), (uint32_t)bc);
-      } else {
-        out[e] = INT32_MIN;
+      for (int r = 0; r < R; r++) {
+        const int32_t xv = xs[r];
+        const bool p = ((uint32_t)xv & 1023u) < (uint32_t)D;
+        const uint64_t P = __builtin_amdgcn_ballot_w64(p);
+        const uint64_t Bq = __builtin_amdgcn_ballot_w64(xv > 0) & P;
+        const uint64_t Aq = __builtin_amdgcn_ballot_w64(((xv >> 10) & 31) == 0) & P;
+        const uint64_t Lq = __builtin_amdgcn_ballot_w64(((xv >> 15) & 31) != 0) & P;
+        // both logical warps' leader values (v_readlane: lanes are uniform)
+        const uint32_t m0 = (uint32_t)P, m1 = (uint32_t)(P >> 32);
+        const int ld0 = m0 ? __builtin_ctz(m0) : 0, ld1 = m1 ? __builtin_ctz(m1) : 0;
+        const int32_t bc0 = __builtin_amdgcn_readlane(xv, ld0), bc1 = __builtin_amdgcn_readlane(xv, 32 + ld1);
+        const uint32_t m = hi ? m1 : m0;
+        // next lane of m above l, wrapping to its first lane
+        const uint32_t above = m & above_mask;
+        const int sl = above ? __builtin_ctz(above) : (m ? __builtin_ctz(m) : l);
+        const int32_t sv = bperm(xv, (hi ? 32 : 0) + sl);
+        dst[r * 256] = p ? sv : INT32_MIN;
+        if (l == 0) {
+          const uint32_t b = hi ? (uint32_t)(Bq >> 32) : (uint32_t)Bq;
+          const uint32_t A = (hi ? (uint32_t)(Aq >> 32) : (uint32_t)Aq) != 0u;
+          const uint32_t L = (hi ? (uint32_t)(Lq >> 32) : (uint32_t)Lq) == m;
+          const uint4 v = m ? make_uint4(m, b, A | (L << 1), (uint32_t)(hi ? bc1 : bc0)) : make_uint4(0u, 0u, 0u, 0u);
+          *(uint4 *)(rdst + r * 32) = v;
+        }
       }
-      if (m == 0u && l == 0) *(uint4 *)(rec + 4 * g) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+      // partial last round: whole logical warps only (n % 32 == 0), so a
+      // warp is either entirely in range or entirely out
+#pragma unroll 1
+      for (int r = 0; r < R; r++) {
+        const int64_t e = base + r * 256 + t;
+        const int64_t e32 = e & ~(int64_t)31;
+        if (e32 >= n) continue;  // uniform per logical warp
+        const int32_t xv = (int32_t)ld_stream1(x + e);
+        const bool p = ((uint32_t)xv & 1023u) < (uint32_t)D;
+        const uint32_t m = ballot(p);
+        const uint32_t b = ballot(xv > 0) & m;
+        const uint32_t A = (ballot(((xv >> 10) & 31) == 0) & m) != 0u;
+        const uint32_t L = (ballot(((xv >> 15) & 31) != 0) & m) == m;
+        const uint32_t above = m & above_mask;
+        const int sl = above ? __builtin_ctz(above) : (m ? __builtin_ctz(m) : l);
+        const int32_t sv = shfl(xv, sl);
+        const int32_t bc = shfl(xv, m ? __builtin_ctz(m) : 0);
+        out[e] = p ? sv : INT32_MIN;
+        if (l == 0)
+          *(uint4 *)(rec + 4 * (e >> 5)) = m ? make_uint4(m, b, A | (L << 1), (uint32_t)bc) : make_uint4(0u, 0u, 0u, 0u);
+      }
     }
   }
 }
@@ -93,11 +161,11 @@ __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__
 using tred_fn = void (*)(const int32_t *, int64_t, int32_t *);
 static tred_fn pick_tile(int T) {
   switch (T) {
-  case 2: return k_tile_reduce<2, 8>;
-  case 4: return k_tile_reduce<4, 8>;
-  case 8: return k_tile_reduce<8, 8>;
-  case 16: return k_tile_reduce<16, 8>;
-  case 32: return k_tile_reduce<32, 8>;
+  case 2: return k_tile_reduce<2, 4>;
+  case 4: return k_tile_reduce<4, 4>;
+  case 8: return k_tile_reduce<8, 4>;
+  case 16: return k_tile_reduce<16, 4>;
+  case 32: return k_tile_reduce<32, 4>;
   }
   return nullptr;
 }
@@ -114,7 +182,7 @@ cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, 
   if (!fn) return COX_ERR_INVALID;
   if (n == 0) return COX_OK;
   if (!x || !out) return COX_ERR_INVALID;
-  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 8 - 1) / (256 * 8), 0, 0, 4);
+  const int grid = persistent_grid((const void *)fn, 256, (n + 1024 * 4 - 1) / (1024 * 4), 0, 0, 4);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, x, n, out);
   return launch_status();
 }

@@ -243,12 +243,24 @@ def test_tile_sort_adversarial_and_zero_one(dev):
 
 # ---------------------------------------------------------------- tile reduce / masked
 @pytest.mark.parametrize("T", [2, 4, 8, 16, 32])
-def test_tile_reduce(dev, oracle_mod, T):
+@pytest.mark.parametrize("n", [1, 7, 256 * 8 * 5 + 37, 4096 * 700 + 4093])
+def test_tile_reduce(dev, oracle_mod, T, n):
     torch, cox = dev
-    n = 256 * 8 * 5 + 37
+    say("tile reduce T", T, "n", n)
     x = inputs.masked_input(n)
     got = down(cox.tile_reduce(up(torch, x), T))
     assert np.array_equal(got, oracle_mod.tile_reduce_i32(x, T))
+
+
+@pytest.mark.parametrize("T", [2, 8, 32])
+def test_tile_reduce_unaligned_input(dev, oracle_mod, T):
+    """x starting 4 bytes past a 16-byte boundary (a tensor view)."""
+    torch, cox = dev
+    n = 4096 * 9 + 301
+    x = inputs.masked_input(n + 1)
+    g = up(torch, x)[1:]
+    got = down(cox.tile_reduce(g, T))
+    assert np.array_equal(got, oracle_mod.tile_reduce_i32(x[1:], T))
 
 
 @pytest.mark.parametrize("D", (0, 1, 102, 512, 922, 1024))
