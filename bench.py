@@ -73,13 +73,14 @@ def cpu_baseline(x, keys, f, sample, sig):
         cores = min(16, os.cpu_count() or 1)
     oracle.set_threads(cores)
     xs, ks, fs = x[:sample].copy(), keys[:sample].copy(), f[:sample].copy()
-    (kr, Wr), (kS, WS), (kC, WC) = sig["reduce"], sig["scan"], sig["compact"]
+    (kr, Wr), (kf, Wf) = sig["reduce_i32"], sig["reduce_f32"]
+    (kS, WS), (kC, WC) = sig["scan"], sig["compact"]
     t0 = time.perf_counter()
     oracle.reduce(xs, kr, Wr)
     oracle.scan_i32(xs, kS, WS)
     oracle.compact_i32(xs, kC, WC)
     oracle.tile_sort_u32(ks)
-    oracle.reduce(fs, kr, Wr)
+    oracle.reduce(fs, kf, Wf)
     dt = time.perf_counter() - t0
     return {"value": round(5 * sample / dt / 1e9, 4), "unit": "GElem/s", "cores": cores, "kind": "oracle",
             "sample": (f"the whole batch ({sample} elements of each input)" if sample == len(x) else
@@ -156,7 +157,7 @@ def other_kernels(fg, reps=10):
     return res
 
 
-def batching(reps=5, base_reps=2):
+def batching(reps=5, base_reps=2, per_segment=True):
     """The segmented workload (10,000 lognormal segments): the fused
     reduce + scan + compaction as one autotuned graph-captured launch vs the
     same kernel launched once per segment, per dtype."""
@@ -194,9 +195,11 @@ def batching(reps=5, base_reps=2):
         alg = 4 * n + 4 * n + 4 * kept + 8 * (nseg + 1) + 16 * nseg
         tot, y, oc, cnt = (torch.empty_like(plan.seg_total), torch.empty_like(plan.y), torch.empty_like(plan.out),
                            torch.empty_like(plan.seg_count))
-        t_seg = timed(lambda: cox.segmented_per_segment(xg, og, torch.from_numpy(off), cfg=(k, W), seg_total=tot,
-                                                        y=y, out=oc, seg_count=cnt), base_reps)
-        same = bool(torch.equal(cnt, plan.seg_count))
+        t_seg, same = None, None
+        if per_segment:
+            t_seg = timed(lambda: cox.segmented_per_segment(xg, og, torch.from_numpy(off), cfg=(k, W), seg_total=tot,
+                                                            y=y, out=oc, seg_count=cnt), base_reps)
+            same = bool(torch.equal(cnt, plan.seg_count))
         plan.close()
         for ws in cox._ws_cache.values():
             ws.status()
@@ -204,9 +207,9 @@ def batching(reps=5, base_reps=2):
                      "batched_gelem_s": round(n / (t_plan * 1e-3) / 1e9, 2),
                      "batched_gb_s": round(alg / (t_plan * 1e-3) / 1e9, 1),
                      "batched_hbm_frac": round(alg / (t_plan * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "per_segment_ms": round(t_seg, 3), "speedup": round(t_seg / t_plan, 2),
-                     "counts_agree": same}
-        log(f"batching {name}: plan {t_plan:.3f} ms, per-segment {t_seg:.2f} ms")
+                     "per_segment_ms": None if t_seg is None else round(t_seg, 3),
+                     "speedup": None if t_seg is None else round(t_seg / t_plan, 2), "counts_agree": same}
+        log(f"batching {name}: plan {t_plan:.3f} ms, per-segment {t_seg} ms")
         del xg
     return res
 
@@ -222,6 +225,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the segmented batching comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the kernels outside the timed step")
+    ap.add_argument("--no-per-segment", action="store_true",
+                    help="skip the one-launch-per-segment baseline of the batching comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -247,15 +252,17 @@ def main():
     srt = torch.empty_like(kg)
     ti = torch.empty(1, dtype=torch.int64, device="cuda")
     tf = torch.empty(1, dtype=torch.float64, device="cuda")
-    sig = {"reduce": cox.default_cfg(cox.OP_REDUCE)[:2], "scan": cox.default_cfg(cox.OP_SCAN)[:2],
-           "compact": cox.default_cfg(cox.OP_COMPACT)[:2]}
+    sig = {"reduce_i32": cox.default_cfg(cox.OP_REDUCE, cox.I32)[:2],
+           "reduce_f32": cox.default_cfg(cox.OP_REDUCE, cox.F32)[:2],
+           "scan": cox.default_cfg(cox.OP_SCAN)[:2], "compact": cox.default_cfg(cox.OP_COMPACT)[:2]}
     sort_k = 4
     # workspaces and partial buffers are allocated once, outside the timed region
-    kr, Wr = sig["reduce"]
-    nch_r = -(-n // (32 * Wr * kr))
-    pi = torch.empty(nch_r, dtype=torch.int32, device="cuda")
-    pf = torch.empty(nch_r, dtype=torch.float32, device="cuda")
+    nch_i = -(-n // (32 * sig["reduce_i32"][1] * sig["reduce_i32"][0]))
+    nch_f = -(-n // (32 * sig["reduce_f32"][1] * sig["reduce_f32"][0]))
+    pi = torch.empty(nch_i, dtype=torch.int32, device="cuda")
+    pf = torch.empty(nch_f, dtype=torch.float32, device="cuda")
     cox.workspace(cox.OP_REDUCE, cox.I32, n)
+    cox.workspace(cox.OP_REDUCE, cox.F32, n)
     cox.workspace(cox.OP_SCAN, cox.I32, n)
     cox.workspace(cox.OP_COMPACT, cox.I32, n)
     # one plain copy of the int32 input (untimed; 1 GiB read + 1 GiB write):
@@ -323,13 +330,12 @@ def main():
     kept = int(cnt.item())
     for ws in cox._ws_cache.values():
         ws.status()  # raises if a cross-block wait gave up
-    nr = nch_r * 4
     alg_bytes = {
-        "reduce_i32": 4 * n + nr,
+        "reduce_i32": 4 * n + 4 * nch_i,
         "scan_i32": 8 * n,
         "compact_i32": 4 * n + 4 * kept + 8,
         "tile_sort_u32": 8 * n,
-        "reduce_f32": 4 * n + nr,
+        "reduce_f32": 4 * n + 4 * nch_f,
     }
     kernels = {}
     for nm in names:
@@ -359,7 +365,8 @@ def main():
         "data": "synthetic (seeded numpy PCG64: int32 U[-2^20, 2^20], uint32 uniform keys, float32 N(0,1))",
         "config": {"workload": "warp primitive set over 2^28 elements: int32 sum, int32 inclusive scan, "
                                "ballot compaction (x > 0), uint32 32-key tile sort, fp32 tree sum",
-                   "n": n, "sigma_reduce": list(sig["reduce"]), "sigma_scan": list(sig["scan"]),
+                   "n": n, "sigma_reduce_i32": list(sig["reduce_i32"]), "sigma_reduce_f32": list(sig["reduce_f32"]),
+                   "sigma_scan": list(sig["scan"]),
                    "sigma_compact": list(sig["compact"]),
                    "sort_keys_per_lane": sort_k},
         "kernels": kernels,
@@ -373,7 +380,7 @@ def main():
     if not args.no_batching:
         del xg, fg
         torch.cuda.empty_cache()
-        out["batching"] = batching()
+        out["batching"] = batching(per_segment=not args.no_per_segment)
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, n)
         log(f"cpu baseline: oracle on {sample} elements")

@@ -343,8 +343,8 @@ def stream_copy(src, dst, grid_blocks=0):
 # ---------------------------------------------------------------- segmented
 SEG_REDUCE, SEG_SCAN, SEG_COMPACT = 1, 2, 4
 
-# the plan autotuner's candidates all use chunks of at least 1024 elements
-_SEG_MIN_CHUNK_CFG = (4, 8)
+# the plan autotuner's candidates all use chunks of at least 4096 elements
+_SEG_MIN_CHUNK_CFG = (8, 16)
 
 
 def _seg_outputs(x, offsets, which, seg_total, y, out, seg_count):

@@ -984,7 +984,7 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
   const bool tune = autotune && (!cfg || (!cfg->items_per_lane && !cfg->warps_per_block));
   if (tune) {
     // candidate schedules and grids, timed on the caller's buffers
-    static const int KW[][2] = {{2, 16}, {4, 8}, {4, 16}, {8, 4}, {8, 8}, {8, 16}, {16, 4}, {16, 8}};
+    static const int KW[][2] = {{8, 16}, {16, 8}, {16, 16}, {8, 32}, {16, 32}};
     const int cus = device_cus();
     float best_ms = -1.0f;
     for (const auto &kw : KW) {
