@@ -18,7 +18,8 @@
 // lane's own earlier slots.  Kept elements are staged in the warp's own
 // shared-memory region at their rank, warp counts are scanned in shared
 // memory, chunk offsets chained by the same look-back, and each warp then
-// writes its run with coalesced stores.
+// writes its run in 16-byte vectors aligned in global memory (the run's
+// ragged first and last vectors element by element).
 //
 // Chunks are claimed from a ticket counter, so a chunk only ever waits for
 // chunks that running blocks already hold.  Every block finally draws one
@@ -29,6 +30,9 @@
 #include "cox_internal.hpp"
 
 namespace cox {
+
+// 16-byte vectors at 4-byte aligned addresses (one dwordx4 access each)
+typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // inclusive scan of v over the 32 lanes of the logical warp (integers)
 __device__ __forceinline__ uint32_t warp_incl_scan_u32(uint32_t v) {
@@ -263,14 +267,27 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
           }
       }
     } else {
-      // the warp writes its kept run [off, off + wval) from its region
+      // the warp writes its kept run [off, off + wval) from its region in
+      // 16-byte vectors aligned in global memory: lane j takes positions
+      // [A + 4j, A + 4j + 4) of each 128-position step, A = off rounded down
+      // to a multiple of 4; the run's partial first and last vectors are
+      // written element by element
       const int32_t *region = s_stage + w * 32 * K;
-      for (uint32_t q = l; q < wval; q += 32) {
-        // the bound only matters if a look-back wait gave up (HDR_ERR set)
-        const uint64_t pos = (uint64_t)off + q;
-        // plain stores: the warp's 4-byte stores of one run are merged into
-        // whole lines in L2 (streaming stores would reach HBM as partial lines)
-        if (pos < (uint64_t)n) out[pos] = region[q];
+      const uint64_t A = (uint64_t)off & ~(uint64_t)3, E = (uint64_t)off + wval;
+      for (uint64_t p = A + 4 * (uint64_t)l; p < E; p += 128) {
+        if (p >= off && p + 4 <= E && p + 4 <= (uint64_t)n) {
+          const int64_t q = (int64_t)(p - off);
+          const u32x4u v = {(uint32_t)region[q], (uint32_t)region[q + 1], (uint32_t)region[q + 2],
+                           (uint32_t)region[q + 3]};
+          *(u32x4u *)(out + p) = v;
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const uint64_t pj = p + j;
+            // the bound on n only matters if a look-back wait gave up
+            if (pj >= off && pj < E && pj < (uint64_t)n) out[pj] = region[pj - off];
+          }
+        }
       }
     }
     return cn;
