@@ -130,3 +130,20 @@ def test_segmented_full_workload(dev, oracle_mod, dtype):
     got = cox.segmented(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(), 7)
     want = oracle_mod.segmented(x, off, k, W)
     check(torch, got, want, off.size - 1)
+
+
+def test_segmented_fp_worked_example(dev, oracle_mod):
+    """The tie-rounding worked example of the oracle tests (2^24 and ones,
+    sigma = (1, 1)): the GPU's FP32 scan tree, FP64 carry and totals give
+    the hand-derived bits."""
+    torch, cox = dev
+    pat = np.ones(32, np.float32)
+    pat[0] = 2.0 ** 24
+    f = np.tile(pat, 3)
+    off = np.array([0, 32, 96], np.int64)
+    got = cox.segmented(torch.from_numpy(f).cuda(), torch.from_numpy(off).cuda(), 7, cfg=(1, 1))
+    check(torch, got, oracle_mod.segmented(f, off, 1, 1), 2)
+    offs = np.array([0, 0, 0, 4, 4, 4, 4, 8, 8, 8, 8, 12, 12, 12, 12, 16,
+                     16, 16, 16, 16, 20, 20, 20, 20, 24, 24, 24, 24, 28, 28, 28, 28], np.float64)
+    want = np.concatenate([2.0 ** 24 + offs, 2.0 ** 24 + offs, 2.0 ** 25 + 28 + offs]).astype(np.float32)
+    assert np.array_equal(got[1].cpu().numpy().view(np.uint32), want.view(np.uint32))

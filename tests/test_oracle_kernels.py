@@ -461,3 +461,41 @@ def test_segment_generator_shape():
     assert off.size == inputs.NSEG + 1 and lens.max() <= inputs.SEG_CAP
     assert 0.9e8 < off[-1] < 2.0e8
     assert 1500 < np.median(lens) < 2600
+
+
+def test_segmented_fp_scan_worked_example(oracle_mod):
+    """A hand-derived worked example of the FP32 chunk scan tree and the
+    FP64 chunk carry at sigma = (1, 1) (one 32-lane warp per chunk):
+    x = 2^24 in lane 0 and 1.0 in lanes 1..31, where every rounding is a
+    tie, so the result depends on the exact order of the additions.
+
+    Row 0 (lanes 0..15), Kogge-Stone shfl_up by 1, 2, 4, 8 (identity below
+    the row start): 2^24 + 1 rounds to 2^24, so r = 2^24 + [0, 0, 2, 2, 4,
+    4, 6, 6, 8, 8, 10, 10, 12, 12, 14, 14].  Row 1 (lanes 16..31) holds
+    1..16 after its own steps, then adds lane 15 (2^24 + 14): 2^24 + 15 + j
+    rounds an odd offset to the multiple of 4 next to it, r = 2^24 + [16,
+    16, 16, 18, 20, 20, 20, 22, 24, 24, 24, 26, 28, 28, 28, 30].  The output
+    q_l = ((E + C) + ex_l) + z_l with E = C = -0.0, ex_l = r_{l-1} (the
+    identity at lane 0) and z_l = x_l: 2^24 + r_{l-1} + 1 again rounds odd
+    offsets to a multiple of 4, giving 2^24 + [0, 0, 0, 4, 4, 4, 4, 8, 8, 8,
+    8, 12, 12, 12, 12, 16, 16, 16, 16, 16, 20, 20, 20, 20, 24, 24, 24, 24,
+    28, 28, 28, 28] (the exact prefix is 2^24 + l, a serial FP32 scan gives
+    2^24 everywhere).  The reduce tree for lane 0 (xor 16, 8, 4, 2, 1):
+    2^24 + 1 -> 2^24, + 2, + 4, + 8, + 16 = 2^24 + 30 (exact sum 2^24 + 31).
+
+    Segments [0, 32) and [32, 96): the second has two chunks; the second
+    chunk's carry is the FP64 sum of the first chunk's total T = q_31 =
+    2^24 + 28, so its outputs are (float)(2^24 + 28 + q_l) = 2^25 + 28 +
+    offset_l (multiples of 4 are exact at 2^25); its total is the FP64 sum
+    of the two partials, 2^25 + 60."""
+    pat = np.ones(32, np.float32)
+    pat[0] = 2.0 ** 24
+    f = np.tile(pat, 3)
+    off = np.array([0, 32, 96], np.int64)
+    tot, y, oc, cnt = oracle_mod.segmented(f, off, 1, 1)
+    offs = np.array([0, 0, 0, 4, 4, 4, 4, 8, 8, 8, 8, 12, 12, 12, 12, 16,
+                     16, 16, 16, 16, 20, 20, 20, 20, 24, 24, 24, 24, 28, 28, 28, 28], np.float64)
+    want = np.concatenate([2.0 ** 24 + offs, 2.0 ** 24 + offs, 2.0 ** 25 + 28 + offs]).astype(np.float32)
+    assert np.array_equal(y.view(np.uint32), want.view(np.uint32))
+    assert tot[0] == 2.0 ** 24 + 30 and tot[1] == 2.0 ** 25 + 60
+    assert np.array_equal(cnt, [32, 64]) and np.array_equal(oc, f)
