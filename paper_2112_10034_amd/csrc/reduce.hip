@@ -275,17 +275,22 @@ __global__ __launch_bounds__(1024) void k_reduce(const void *__restrict__ x, con
   const int64_t S = (int64_t)blockDim.x * K;
 
   // Full chunks c = blockIdx.x + i * gridDim.x run double-buffered: the
-  // next chunk's vectors are requested (unconditionally, from a clamped
-  // chunk index) before the current chunk is reduced, so loads stay in
-  // flight across the block's barriers.  The partial last chunk (if any) is
-  // reduced afterwards with element-wise bounds.
+  // next chunk's vectors are requested before the current chunk is
+  // reduced, so loads stay in flight across the block's barriers.  Past the
+  // block's last full chunk the request is kept (loads stay unconditional)
+  // but every lane reads the array's first vector: one line, not a chunk.
+  // The partial last chunk (if any) is reduced afterwards with element-wise
+  // bounds.
   const int64_t nfull = n / S;
   auto load_full = [&](int64_t c, uint32_t (&xr)[R][V], uint32_t (&yr)[R][V]) {
-    const int64_t wbase = c * S + (int64_t)w * 32 * K;
+    const bool dummy = c >= nfull;
+    // one base index and one row stride per lane (not a select per load)
+    const int64_t b0 = dummy ? 0 : c * S + (int64_t)w * 32 * K + (int64_t)l * V;
+    const int rs = dummy ? 0 : 32 * V;
 #pragma unroll
     for (int i = 0; i < R; i++) {
-      load_vec<ESZ, V>(x, wbase + (int64_t)(i * 32 + l) * V, xr[i]);
-      if constexpr (OP == OP_DOT) load_vec<ESZ, V>(y, wbase + (int64_t)(i * 32 + l) * V, yr[i]);
+      load_vec<ESZ, V>(x, b0 + (int64_t)i * rs, xr[i]);
+      if constexpr (OP == OP_DOT) load_vec<ESZ, V>(y, b0 + (int64_t)i * rs, yr[i]);
     }
   };
   auto reduce_chunk = [&](int64_t c, const uint32_t (&xr)[R][V], const uint32_t (&yr)[R][V]) {
@@ -307,15 +312,15 @@ __global__ __launch_bounds__(1024) void k_reduce(const void *__restrict__ x, con
   if (nfull > 0) {
     uint32_t xa[R][V], ya[R][V], xb[R][V], yb[R][V];
     int64_t c = blockIdx.x;
-    load_full(c < nfull ? c : nfull - 1, xa, ya);
+    load_full(c, xa, ya);
     while (c < nfull) {
       int64_t cn = c + gridDim.x;
-      load_full(cn < nfull ? cn : c, xb, yb);
+      load_full(cn, xb, yb);
       reduce_chunk(c, xa, ya);
       c = cn;
       if (c >= nfull) break;
       cn = c + gridDim.x;
-      load_full(cn < nfull ? cn : c, xa, ya);
+      load_full(cn, xa, ya);
       reduce_chunk(c, xb, yb);
       c = cn;
     }

@@ -131,6 +131,9 @@ __global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ 
     const int64_t s = base + t;
     uint32_t cnt = 0u;
     if (s < nseg) {
+      // this call's layout of the workspace depends on its segment and
+      // chunk counts, so counters are cleared by every call, not assumed
+      ws.done[s] = 0u;
       int64_t a, b;
       seg_bounds(off, s, n, a, b);
       const int64_t len = b - a;
@@ -175,6 +178,11 @@ __global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ 
   }
 }
 
+// zero words [0, words) (the per-segment baseline's workspace region)
+__global__ __launch_bounds__(256) void k_seg_clear(uint32_t *p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256) p[i] = 0u;
+}
+
 // one logical warp per segment: the descriptors of its chunks
 __global__ __launch_bounds__(256) void k_seg_map(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
                                                  SegWS ws) {
@@ -192,7 +200,17 @@ __global__ __launch_bounds__(256) void k_seg_map(const int64_t *__restrict__ off
     d.lo = c0;
     d.nchs = c1 - c0;
     d.pad = 0u;
-    for (uint32_t c = c0 + l; c < c1; c += 32) ws.desc[c] = d;
+    for (uint32_t c = c0 + l; c < c1; c += 32) {
+      ws.desc[c] = d;
+      // the chunk's cross-block words start with tag 0 (no call's tag):
+      // this memory may hold another layout's words from an earlier call
+      ws.w_scan[c] = 0;
+      ws.w_cnt[c] = 0;
+      ws.w_part[c] = 0;
+      ws.w_tot[c] = 0;
+      ws.w_ph[c] = 0;
+      ws.w_pl[c] = 0;
+    }
   }
 }
 
@@ -941,6 +959,18 @@ cox_status cox_segmented_per_segment(const void *x, cox_dtype dtype, const int64
   for (int64_t s = 0; s <= nseg; s++)
     if (offsets_host[s] < 0 || offsets_host[s] > n || (s > 0 && offsets_host[s] < offsets_host[s - 1]))
       return COX_ERR_INVALID;
+  {
+    // counters and tagged words of this layout start cleared
+    size_t used = 0;
+    seg_layout(ws, nseg, n / S + nseg + 1, &used);
+    const int64_t words = (int64_t)(used - WS_HEADER) / 4;
+    int cg = (int)((words + 255) / 256);
+    cg = cg < 1 ? 1 : (cg > 4096 ? 4096 : cg);
+    hipLaunchKernelGGL(k_seg_clear, dim3(cg), dim3(256), 0, (hipStream_t)stream,
+                       (uint32_t *)((char *)ws + WS_HEADER), words);
+    st = launch_status();
+    if (st != COX_OK) return st;
+  }
   for (int64_t s = 0; s < nseg; s++) {
     const int64_t len = offsets_host[s + 1] - offsets_host[s];
     const int64_t nc = (len + S - 1) / S;

@@ -147,3 +147,25 @@ def test_segmented_fp_worked_example(dev, oracle_mod):
                      16, 16, 16, 16, 20, 20, 20, 20, 24, 24, 24, 24, 28, 28, 28, 28], np.float64)
     want = np.concatenate([2.0 ** 24 + offs, 2.0 ** 24 + offs, 2.0 ** 25 + 28 + offs]).astype(np.float32)
     assert np.array_equal(got[1].cpu().numpy().view(np.uint32), want.view(np.uint32))
+
+
+def test_workspace_reuse_across_layouts(dev, oracle_mod):
+    """Calls with different segment counts and schedules share the cached
+    workspace, whose layout moves with them: each call must start from
+    cleared counters and words, whatever the previous call left there."""
+    torch, cox = dev
+    off_a, xa, _ = small_case()
+    rng = np.random.default_rng(7)
+    lens = rng.integers(0, 300, size=400)
+    off_b = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    xb, _ = inputs.segment_values(int(off_b[-1]), seed=99)
+    cases = [(off_a, xa, (16, 16)), (off_b, xb, (1, 1)), (off_a, xa, (2, 16)), (off_b, xb, (8, 4)),
+             (off_a, xa, (1, 1))]
+    for rep in range(2):
+        for off, x, cfg in cases:
+            print("layout case", off.size - 1, "segments, sigma", cfg, flush=True)
+            got = cox.segmented(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(), 7, cfg=cfg)
+            check(torch, got, oracle_mod.segmented(x, off, *cfg), off.size - 1)
+            got = cox.segmented_per_segment(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(),
+                                            torch.from_numpy(off), cfg=cfg)
+            check(torch, got, oracle_mod.segmented(x, off, *cfg), off.size - 1)
