@@ -15,9 +15,11 @@
 //
 // Compaction: p = (x > 0); per row and vector slot v a ballot B_v; the
 // rank of (l, v) inside the row is sum_v' popc(B_v' & lanemask_lt) plus the
-// lane's own earlier slots.  Kept elements are staged in the warp's own
-// shared-memory region at their rank, warp counts are scanned in shared
-// memory, chunk offsets chained by the same look-back, and each warp then
+// lane's own earlier slots (mbcnt over the wave's 64-bit ballots).  Kept
+// elements are staged in the warp's own shared-memory region at their rank
+// (the others in a trash slot, without branches), warp counts are scanned
+// in shared memory, chunk offsets chained by the same look-back, and each
+// warp then
 // writes its run in 16-byte vectors aligned in global memory (the run's
 // ragged first and last vectors element by element).
 //
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
   __syncthreads();
   const uint32_t epoch = s_epoch;
   const uint32_t tag = tag_of_epoch(epoch);
-  const uint32_t lt = lanemask_lt();
+  const bool hi_half = lhalf() != 0;
 
   // vectors of chunk c; with dummy set every lane reads the array's first
   // vector instead (a ticket past the full chunks: keeps the loads
@@ -196,25 +198,33 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
         wval += (uint32_t)bcast31((int)incl);
       }
     } else {
-      // ranks inside the warp from ballots; kept elements go to the warp's
-      // own shared-memory region at their rank (written and later read by
-      // the same warp, so no block barrier is needed for it)
-      int32_t *region = s_stage + w * 32 * K;
+      // ranks inside the warp from ballots: the wave's 64-bit ballot, lanes
+      // below counted by mbcnt (an upper-half lane also counts the whole
+      // lower half, subtracted once per row); kept elements go to the
+      // warp's own shared-memory region at their rank, the others to the
+      // lane's trash slot past the region (no branches).  The region is
+      // written and later read by the same warp: no block barrier.
+      int32_t *region = s_stage + w * (32 * K + 32);
+      const uint32_t trash = 32 * K + l;
 #pragma unroll
       for (int i = 0; i < R; i++) {
-        uint32_t base = 0u, rowcnt = 0u, own = 0u;
+        uint32_t base = 0u, lo_cnt = 0u, hi_cnt = 0u;
 #pragma unroll
         for (int j = 0; j < V; j++) {
-          const uint32_t B = ballot((int32_t)cur[i][j] > 0);
-          base += __popc(B & lt);
-          rowcnt += __popc(B);
+          const uint64_t B = __builtin_amdgcn_ballot_w64((int32_t)cur[i][j] > 0);
+          base = __builtin_amdgcn_mbcnt_hi((uint32_t)(B >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)B, base));
+          lo_cnt += __builtin_popcount((uint32_t)B);
+          hi_cnt += __builtin_popcount((uint32_t)(B >> 32));
         }
+        if (hi_half) base -= lo_cnt;
+        uint32_t pos = wval + base;
 #pragma unroll
         for (int j = 0; j < V; j++) {
-          if ((int32_t)cur[i][j] > 0) region[wval + base + own] = (int32_t)cur[i][j];
-          own += (int32_t)cur[i][j] > 0 ? 1u : 0u;
+          const bool k = (int32_t)cur[i][j] > 0;
+          region[k ? pos : trash] = (int32_t)cur[i][j];
+          pos += k ? 1u : 0u;
         }
-        wval += rowcnt;
+        wval += hi_half ? hi_cnt : lo_cnt;
       }
     }
     if (l == 0) s_w[w] = wval;
@@ -271,22 +281,22 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
       // 16-byte vectors aligned in global memory: lane j takes positions
       // [A + 4j, A + 4j + 4) of each 128-position step, A = off rounded down
       // to a multiple of 4; the run's partial first and last vectors are
-      // written element by element
-      const int32_t *region = s_stage + w * 32 * K;
-      const uint64_t A = (uint64_t)off & ~(uint64_t)3, E = (uint64_t)off + wval;
-      for (uint64_t p = A + 4 * (uint64_t)l; p < E; p += 128) {
-        if (p >= off && p + 4 <= E && p + 4 <= (uint64_t)n) {
-          const int64_t q = (int64_t)(p - off);
-          const u32x4u v = {(uint32_t)region[q], (uint32_t)region[q + 1], (uint32_t)region[q + 2],
-                           (uint32_t)region[q + 3]};
-          *(u32x4u *)(out + p) = v;
+      // written element by element.  Offsets below are relative to A.
+      const int32_t *region = s_stage + w * (32 * K + 32);
+      const uint64_t A = (uint64_t)off & ~(uint64_t)3;
+      const uint32_t head = (uint32_t)((uint64_t)off - A);  // 0..3 positions before the run
+      uint32_t span = head + wval;
+      // the bound on n only matters if a look-back wait gave up
+      if (A + span > (uint64_t)n) span = A < (uint64_t)n ? (uint32_t)((uint64_t)n - A) : 0u;
+      int32_t *dst = out + A;
+      for (uint32_t t = 4u * (uint32_t)l; t < span; t += 128u) {
+        if (t >= head && t + 4u <= span) {
+          const u32x4u v = *(const u32x4u *)(region + (t - head));
+          *(u32x4u *)(dst + t) = v;
         } else {
 #pragma unroll
-          for (int j = 0; j < 4; j++) {
-            const uint64_t pj = p + j;
-            // the bound on n only matters if a look-back wait gave up
-            if (pj >= off && pj < E && pj < (uint64_t)n) out[pj] = region[pj - off];
-          }
+          for (uint32_t j = 0; j < 4u; j++)
+            if (t + j >= head && t + j < span) dst[t + j] = region[t + j - head];
         }
       }
     }
@@ -379,7 +389,7 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
   lb_fn fn = pick_lb<MODE_COMPACT>(sg.k);
   if (!fn) return COX_ERR_UNSUPPORTED;
   const int block = 32 * sg.W;
-  const size_t lds = (size_t)block * sg.k * sizeof(int32_t) + 256;  // staging + static
+  const size_t lds = (size_t)sg.W * (32 * sg.k + 32) * sizeof(int32_t) + 256;  // staging (+ trash) + static
   if (lds > device_max_lds()) return COX_ERR_UNSUPPORTED;
   if (lds - 256 > 64 * 1024 &&
       hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(lds - 256)) != hipSuccess)
