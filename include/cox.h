@@ -252,8 +252,9 @@ cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *ou
  * non-decreasing, within [0, n]; x: device int32 or float32 [n], 16-byte
  * aligned).  Offsets cannot be checked before launch; the kernels clamp
  * every segment to [0, n] (a reversed segment is empty), so bad offsets
- * give meaningless results but no access outside x.  Chunks of S = 32 * warps_per_block * items_per_lane
- * elements start at each segment's first element (items_per_lane <= 16).
+ * give meaningless results but no access outside x.  Chunks of
+ * S = 32 * warps_per_block * items_per_lane elements start at each
+ * segment's first element (items_per_lane <= 32).
  *   seg_total[s] : device int64 (int32 input) = sum of the int32-wrapped
  *                  chunk partials as int64; device double (float input) =
  *                  FP64 sum, from -0.0 in chunk order, of the chunk

@@ -194,9 +194,10 @@ cox_status cox_default_cfg(cox_op op, cox_dtype dtype, cox_cfg *out) {
     out->warps_per_block = 32;
     break;
   case COX_OP_SEGMENTED:
-    // measured on the 10,000-segment lognormal workload
-    out->items_per_lane = 16;
-    out->warps_per_block = 16;
+    // measured on the 10,000-segment lognormal workload: 256-thread blocks
+    // of 8192-element chunks (four blocks per compute unit)
+    out->items_per_lane = 32;
+    out->warps_per_block = 8;
     break;
   default: return COX_ERR_INVALID;
   }

@@ -766,6 +766,7 @@ static seg_fn pick_seg_k(int k) {
   case 4: return k_segmented<4, DT>;
   case 8: return k_segmented<8, DT>;
   case 16: return k_segmented<16, DT>;
+  case 32: return k_segmented<32, DT>;
   }
   return nullptr;
 }
@@ -803,7 +804,7 @@ static cox_status seg_prepare(const void *x, cox_dtype dt, const int64_t *offset
   Sigma sg;
   cox_status st = resolve_cfg(COX_OP_SEGMENTED, dt, cfg, &sg);
   if (st != COX_OK) return st;
-  if (sg.k > 16) return COX_ERR_UNSUPPORTED;
+  if (sg.k > 32) return COX_ERR_UNSUPPORTED;
   const int64_t S = (int64_t)32 * sg.W * sg.k;
   const int64_t maxch = n / S + nseg + 1;
   if (maxch > 0x7fffffffLL - 65536 || nseg > 0x7fffffffLL) return COX_ERR_INVALID;
@@ -1014,7 +1015,7 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
   const bool tune = autotune && (!cfg || (!cfg->items_per_lane && !cfg->warps_per_block));
   if (tune) {
     // candidate schedules and grids, timed on the caller's buffers
-    static const int KW[][2] = {{8, 16}, {16, 8}, {16, 16}, {8, 32}, {16, 32}};
+    static const int KW[][2] = {{16, 8}, {16, 16}, {32, 8}, {32, 16}, {8, 32}};
     const int cus = device_cus();
     float best_ms = -1.0f;
     for (const auto &kw : KW) {

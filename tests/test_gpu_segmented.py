@@ -8,7 +8,7 @@ from paper_2112_10034_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-SIGMAS = [(1, 1), (4, 8), (8, 4), (16, 8), (2, 16), (8, 16), (16, 4)]
+SIGMAS = [(1, 1), (4, 8), (8, 4), (16, 8), (2, 16), (8, 16), (16, 4), (32, 8), (32, 2)]
 
 
 @pytest.fixture(scope="module")
