@@ -5,7 +5,8 @@
 // built from per-lane predicates.  A block handles R rows of 256
 // consecutive elements per round (coalesced streaming 4-byte loads, R loads
 // in flight per thread), and the whole block runs every round so that the
-// exchanges always see full warps.
+// exchanges always see full warps (16 rows per round, eight blocks per
+// compute unit).
 //
 // Tile reductions are int32 sums modulo 2^32, whose value does not depend
 // on the order of the additions, so the kernel loads 16-byte vectors: a
@@ -87,6 +88,13 @@ __global__ __launch_bounds__(256) void k_tile_reduce(const int32_t *__restrict__
 // The stored values are those of the divergent CUDA code, whose lanes of m
 // are exactly the lanes that would execute it.  The warp's record is
 // written by its logical lane 0 (same bytes as writing it from the leader).
+// v with lane 32 replaced by the wave-uniform value u (v_writelane writes
+// one lane of a vector register, whatever the execution mask)
+__device__ __forceinline__ uint32_t with_lane32(uint32_t v, uint32_t u) {
+  asm volatile("v_writelane_b32 %0, %1, 32" : "+v"(v) : "s"(__builtin_amdgcn_readfirstlane((int)u)));
+  return v;
+}
+
 template <int R>
 __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__ x, int64_t n, int D,
                                                      int32_t *__restrict__ out, uint32_t *__restrict__ rec) {
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__
     if (base + per_block <= n) {
       const int32_t *src = x + base + t;
       int32_t *dst = out + base + t;
-      uint32_t *rdst = rec + 4 * ((base + t) >> 5);
+      uint32_t *rdst = rec + 4 * ((base + t) >> 5);  // lanes 0 and 32: their warp's record
       int32_t xs[R];
 #pragma unroll
       for (int r = 0; r < R; r++) xs[r] = (int32_t)ld_stream1(src + r * 256);
@@ -112,23 +120,30 @@ __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__
         const bool p = ((uint32_t)xv & 1023u) < (uint32_t)D;
         const uint64_t P = __builtin_amdgcn_ballot_w64(p);
         const uint64_t Bq = __builtin_amdgcn_ballot_w64(xv > 0) & P;
-        const uint64_t Aq = __builtin_amdgcn_ballot_w64(((xv >> 10) & 31) == 0) & P;
-        const uint64_t Lq = __builtin_amdgcn_ballot_w64(((xv >> 15) & 31) != 0) & P;
-        // both logical warps' leader values (v_readlane: lanes are uniform)
+        const uint64_t Aq = __builtin_amdgcn_ballot_w64((xv & 0x7c00) == 0) & P;
+        const uint64_t Lq = __builtin_amdgcn_ballot_w64((xv & 0xf8000) != 0) & P;
         const uint32_t m0 = (uint32_t)P, m1 = (uint32_t)(P >> 32);
-        const int ld0 = m0 ? __builtin_ctz(m0) : 0, ld1 = m1 ? __builtin_ctz(m1) : 0;
-        const int32_t bc0 = __builtin_amdgcn_readlane(xv, ld0), bc1 = __builtin_amdgcn_readlane(xv, 32 + ld1);
         const uint32_t m = hi ? m1 : m0;
-        // next lane of m above l, wrapping to its first lane
+        // next lane of m above l, wrapping to its first lane (lanes outside
+        // m read some lane of their half and discard it)
         const uint32_t above = m & above_mask;
-        const int sl = above ? __builtin_ctz(above) : (m ? __builtin_ctz(m) : l);
+        const uint32_t sm = above ? above : m;
+        const int sl = sm ? __builtin_ctz(sm) : 0;
         const int32_t sv = bperm(xv, (hi ? 32 : 0) + sl);
         dst[r * 256] = p ? sv : INT32_MIN;
         if (l == 0) {
-          const uint32_t b = hi ? (uint32_t)(Bq >> 32) : (uint32_t)Bq;
-          const uint32_t A = (hi ? (uint32_t)(Aq >> 32) : (uint32_t)Aq) != 0u;
-          const uint32_t L = (hi ? (uint32_t)(Lq >> 32) : (uint32_t)Lq) == m;
-          const uint4 v = m ? make_uint4(m, b, A | (L << 1), (uint32_t)(hi ? bc1 : bc0)) : make_uint4(0u, 0u, 0u, 0u);
+          // both warps' records from wave-uniform values: lane 0 stores the
+          // lower warp's, lane 32 (set by v_writelane) the upper warp's
+          const int ld0 = m0 ? __builtin_ctz(m0) : 0, ld1 = m1 ? __builtin_ctz(m1) : 0;
+          const uint32_t bc0 = m0 ? (uint32_t)__builtin_amdgcn_readlane(xv, ld0) : 0u;
+          const uint32_t bc1 = m1 ? (uint32_t)__builtin_amdgcn_readlane(xv, 32 + ld1) : 0u;
+          const uint32_t f0 = m0 ? (((uint32_t)Aq != 0u) | ((uint32_t)((uint32_t)Lq == m0) << 1)) : 0u;
+          const uint32_t f1 = m1 ? (((uint32_t)(Aq >> 32) != 0u) | ((uint32_t)((uint32_t)(Lq >> 32) == m1) << 1)) : 0u;
+          uint4 v;
+          v.x = with_lane32(m0, m1);
+          v.y = with_lane32((uint32_t)Bq, (uint32_t)(Bq >> 32));
+          v.z = with_lane32(f0, f1);
+          v.w = with_lane32(bc0, bc1);
           *(uint4 *)(rdst + r * 32) = v;
         }
       }
@@ -193,8 +208,8 @@ cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *ou
   if (n == 0) return COX_OK;
   if (!x || !out || !rec) return COX_ERR_INVALID;
   if (!aligned16(rec)) return COX_ERR_ALIGN;
-  auto fn = k_warp_masked<8>;
-  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 8 - 1) / (256 * 8), 0, 0, 4);
+  auto fn = k_warp_masked<16>;
+  const int grid = persistent_grid((const void *)fn, 256, (n + 256 * 16 - 1) / (256 * 16), 0, 0, 8);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, x, n, density, out, rec);
   return launch_status();
 }
