@@ -80,14 +80,6 @@ __global__ __launch_bounds__(256) void k_tile_reduce(const int32_t *__restrict__
   }
 }
 
-// The masked operations without a divergent branch: every ballot is taken
-// once over the whole wave (a wave-uniform 64-bit value in scalar
-// registers), each logical warp's mask m, its ballot b, any / all results
-// and leader broadcast are derived from the half of that value, and every
-// lane computes its shuffle; lanes outside m then store INT32_MIN instead.
-// The stored values are those of the divergent CUDA code, whose lanes of m
-// are exactly the lanes that would execute it.  The warp's record is
-// written by its logical lane 0 (same bytes as writing it from the leader).
 // v with lane 32 replaced by the wave-uniform value u (v_writelane writes
 // one lane of a vector register, whatever the execution mask)
 __device__ __forceinline__ uint32_t with_lane32(uint32_t v, uint32_t u) {
@@ -95,6 +87,15 @@ __device__ __forceinline__ uint32_t with_lane32(uint32_t v, uint32_t u) {
   return v;
 }
 
+// The masked operations without a divergent branch: every ballot is taken
+// once over the whole wave (a wave-uniform 64-bit value in scalar
+// registers), each logical warp's mask m, its ballot b, any / all results
+// and leader broadcast are derived from the half of that value, and every
+// lane computes its shuffle; lanes outside m then store INT32_MIN instead.
+// The stored values are those of the divergent CUDA code, whose lanes of m
+// are exactly the lanes that would execute it.  Both warps' records are
+// computed from the wave-uniform values; logical lane 0 of each warp
+// writes its warp's (the same bytes as writing it from the leader).
 template <int R>
 __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__ x, int64_t n, int D,
                                                      int32_t *__restrict__ out, uint32_t *__restrict__ rec) {
