@@ -64,6 +64,7 @@ def lib():
             "coxo_tile_sort_u32": (I, [P, P, I64, I]),
             "coxo_tile_reduce_i32": (I, [P, I64, I, P]),
             "coxo_warp_masked": (I, [P, I64, I, P, P]),
+            "coxo_warp_dynamic": (I, [P, I64, I, P, P, P, P, P]),
             "coxo_segmented": (I, [P, I, P, I64, I, I, P, P, P, P]),
             "coxo_exact_sum": (I, [P, P, I, I64, P]),
             "coxo_exact_sum_f64": (I, [P, I64, P]),
@@ -229,6 +230,22 @@ def warp_masked(x, D):
     rec = np.zeros(4 * (x.size // 32), np.uint32)
     _check(lib().coxo_warp_masked(_p(x), x.size, D, _p(out), _p(rec)), "warp_masked")
     return out, rec.reshape(-1, 4)
+
+
+def warp_dynamic(x, D):
+    """Dynamic groups (coalesced_threads, match_any / match_all, the six
+    reduce_*_sync, warp-aggregated append).  Returns (match_any[n],
+    rank[n], rec[n/32, 8], filtered[:count], count); the order of the warps'
+    runs in ``filtered`` is the order the appends happened to take."""
+    x = _c(x, np.int32)
+    mm = np.empty(x.size, np.uint32)
+    rank = np.empty(x.size, np.uint32)
+    rec = np.zeros(8 * (x.size // 32), np.uint32)
+    filt = np.zeros(x.size, np.int32)
+    cnt = np.zeros(1, np.int64)
+    _check(lib().coxo_warp_dynamic(_p(x), x.size, D, _p(mm), _p(rank), _p(rec), _p(filt), _p(cnt)), "warp_dynamic")
+    c = int(cnt[0])
+    return mm, rank, rec.reshape(-1, 8), filt[:c], c
 
 
 def segmented(x, offsets, k, W):

@@ -157,6 +157,53 @@ static int wf_all(const xch_t *x, int l, uint32_t mask) {
   return wf_ballot(x, l, mask) == mask;
 }
 
+/* __match_any_sync: the lanes of the mask whose operand equals the
+ * caller's; __match_all_sync: the mask if every lane of it holds the same
+ * operand (pred = 1), else 0 (pred = 0) */
+static uint32_t wf_match_any(const xch_t *x, int l, uint32_t mask) {
+  if (!call_ok(x, l, mask)) return 0;
+  uint32_t r = 0;
+  for (int i = 0; i < 32; i++)
+    if (((mask >> i) & 1u) && x->v[i] == x->v[l]) r |= 1u << i;
+  return r;
+}
+static uint32_t wf_match_all(const xch_t *x, int l, uint32_t mask, int *pred) {
+  *pred = 0;
+  if (!call_ok(x, l, mask)) return 0;
+  for (int i = 0; i < 32; i++)
+    if (((mask >> i) & 1u) && x->v[i] != x->v[l]) return 0;
+  *pred = 1;
+  return mask;
+}
+
+/* __reduce_{add,min,max,and,or,xor}_sync over the lanes of the mask:
+ * add / and / or / xor on unsigned operands (add wraps), min / max on
+ * signed int operands */
+enum { RD_ADD = 0, RD_MIN, RD_MAX, RD_AND, RD_OR, RD_XOR };
+static uint32_t wf_reduce(const xch_t *x, int l, uint32_t mask, int op) {
+  if (!call_ok(x, l, mask)) return 0;
+  int first = 1;
+  uint32_t r = 0;
+  for (int i = 0; i < 32; i++) {
+    if (!((mask >> i) & 1u)) continue;
+    const uint32_t v = (uint32_t)x->v[i];
+    if (first) {
+      r = v;
+      first = 0;
+      continue;
+    }
+    switch (op) {
+    case RD_ADD: r = r + v; break;
+    case RD_MIN: r = (int32_t)v < (int32_t)r ? v : r; break;
+    case RD_MAX: r = (int32_t)v > (int32_t)r ? v : r; break;
+    case RD_AND: r &= v; break;
+    case RD_OR: r |= v; break;
+    case RD_XOR: r ^= v; break;
+    }
+  }
+  return r;
+}
+
 /* loop peeling of a branch that encloses a barrier: every lane evaluated the
  * condition; it must agree across lanes; lane 0's outcome is followed */
 static int peel(const int *flag, int nlanes) {
@@ -1276,6 +1323,115 @@ int coxo_warp_masked(const int32_t *x, int64_t n, int D, int32_t *out, uint32_t 
   if (n < 0 || n % 32 || D < 0 || D > 1024) return COXO_ERR_INVALID;
   mask_ctx c = {x, D, out, rec};
   return run_blocks(n / 32, mask_block, &c);
+}
+
+/* ================================================================== */
+/* dynamic groups: the lanes whose predicate holds form, inside the     */
+/* divergent branch, the group coalesced_threads() returns (the dynamic */
+/* cooperative group the paper's Table 1 lists as unsupported by COX,   */
+/* filter_arr; Sec. 2.2.2-2.2.3).  Lane l of warp g, x = x[32g + l]:     */
+/*   p = ((uint32)x & 1023) < D;                                         */
+/*   if (p) { grp = coalesced_threads();  m = activemask();             */
+/*     rank[e] = grp.thread_rank();  key = ((uint32)x >> 10) & 7;        */
+/*     mm[e] = __match_any_sync(m, key);                                 */
+/*     ma = __match_all_sync(m, key, &pred);                             */
+/*     the six __reduce_*_sync(m, .) of x (add of x & 0xffff);           */
+/*     filter: the rank-0 lane adds grp.size() to the counter, the base  */
+/*     comes back by grp.shfl(base, 0), out[base + rank] = x;           */
+/*     the rank-0 lane writes rec[g] = {m, ma, add, min, max, and, or,   */
+/*     xor} }                                                           */
+/*   else { mm[e] = 0; rank[e] = 0xffffffff; }                           */
+/*   (m == 0: lane 0 writes rec[g] = 0).                                 */
+/* The counter's order across warps is the order the atomics happen to  */
+/* take; inside a warp the members are written in rank order.            */
+/* ================================================================== */
+typedef struct {
+  const int32_t *x;
+  int D;
+  uint32_t *mm, *rank, *rec;
+  int32_t *filt;
+  int64_t *counter;
+} dyn_ctx;
+
+static void dyn_block(void *p, int64_t g) {
+  dyn_ctx *c = (dyn_ctx *)p;
+  const int32_t *x = c->x + 32 * g;
+  int pr[32];
+  uint32_t m[32], rk[32], mm[32], ma[32], red[6][32];
+  int pred[32];
+  int64_t base[32];
+  xch_t X;
+  xch_war(&X);
+  for (int l = 0; l < 32; l++) pr[l] = ((uint32_t)x[l] & 1023u) < (uint32_t)c->D;
+  /* divergent branch: the intra-warp loops run only the lanes with p */
+  uint32_t active = 0;
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) active |= 1u << l;
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) {
+      m[l] = active; /* activemask() inside the branch */
+      rk[l] = (uint32_t)popc32(active & ((1u << l) - 1u));
+    }
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) xch_put(&X, l, ((uint32_t)x[l] >> 10) & 7u);
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) mm[l] = wf_match_any(&X, l, m[l]);
+  xch_war(&X);
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) xch_put(&X, l, ((uint32_t)x[l] >> 10) & 7u);
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) ma[l] = wf_match_all(&X, l, m[l], &pred[l]);
+  xch_war(&X);
+  for (int op = RD_ADD; op <= RD_XOR; op++) {
+    for (int l = 0; l < 32; l++)
+      if (pr[l]) xch_put(&X, l, op == RD_ADD ? ((uint32_t)x[l] & 0xffffu) : (uint32_t)x[l]);
+    for (int l = 0; l < 32; l++)
+      if (pr[l]) red[op][l] = wf_reduce(&X, l, m[l], op);
+    xch_war(&X);
+  }
+  /* warp-aggregated append */
+  for (int l = 0; l < 32; l++)
+    if (pr[l] && rk[l] == 0)
+      base[l] = __atomic_fetch_add(c->counter, (int64_t)popc32(m[l]), __ATOMIC_RELAXED);
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) xch_put(&X, l, rk[l] == 0 ? (uint64_t)base[l] : 0u);
+  for (int l = 0; l < 32; l++)
+    if (pr[l]) {
+      /* grp.shfl(v, 0): the member of rank 0 is the mask's first lane */
+      const int ld = __builtin_ctz(m[l]);
+      base[l] = (int64_t)wf_shfl(&X, l, m[l], SH_IDX, ld, 32);
+    }
+  xch_war(&X);
+  for (int l = 0; l < 32; l++) {
+    const int64_t e = 32 * g + l;
+    if (pr[l]) {
+      c->mm[e] = mm[l];
+      c->rank[e] = rk[l];
+      c->filt[base[l] + rk[l]] = x[l];
+      if (rk[l] == 0) {
+        uint32_t *r = c->rec + 8 * g;
+        r[0] = m[l];
+        r[1] = ma[l];
+        for (int op = 0; op < 6; op++) r[2 + op] = red[op][l];
+        (void)pred[l];
+      }
+    } else {
+      c->mm[e] = 0;
+      c->rank[e] = 0xffffffffu;
+    }
+    if (l == 0 && active == 0) {
+      uint32_t *r = c->rec + 8 * g;
+      for (int i = 0; i < 8; i++) r[i] = 0;
+    }
+  }
+}
+
+int coxo_warp_dynamic(const int32_t *x, int64_t n, int D, uint32_t *mm, uint32_t *rank, uint32_t *rec,
+                      int32_t *filt, int64_t *count) {
+  if (n < 0 || n % 32 || D < 0 || D > 1024) return COXO_ERR_INVALID;
+  *count = 0;
+  dyn_ctx c = {x, D, mm, rank, rec, filt, count};
+  return run_blocks(n / 32, dyn_block, &c);
 }
 
 /* ================================================================== */

@@ -499,3 +499,65 @@ def test_segmented_fp_scan_worked_example(oracle_mod):
     assert np.array_equal(y.view(np.uint32), want.view(np.uint32))
     assert tot[0] == 2.0 ** 24 + 30 and tot[1] == 2.0 ** 25 + 60
     assert np.array_equal(cnt, [32, 64]) and np.array_equal(oc, f)
+
+
+# ---------------------------------------------------------------- dynamic groups
+def _dyn_plain(x, D):
+    """Plain definitions of the dynamic-group workload per warp: members
+    p = (x & 1023) < D, their mask, ranks, match sets and reductions."""
+    u = x.view(np.uint32).reshape(-1, 32)
+    p = (u & 1023) < D
+    bit = (np.uint64(1) << np.arange(32, dtype=np.uint64))
+    m = (p.astype(np.uint64) * bit).sum(1).astype(np.uint32)
+    rank = np.where(p, np.cumsum(p, axis=1) - 1, 0xFFFFFFFF).astype(np.uint32)
+    keys = (u >> 10) & 7
+    same = (keys[:, :, None] == keys[:, None, :]) & p[:, None, :]
+    mm = np.where(p, (same.astype(np.uint64) * bit).sum(2), 0).astype(np.uint32)
+    rec = np.zeros((u.shape[0], 8), np.uint32)
+    for g in range(u.shape[0]):
+        if not p[g].any():
+            continue
+        v = u[g][p[g]]
+        k = keys[g][p[g]]
+        rec[g] = [m[g], m[g] if (k == k[0]).all() else 0, int((v & 0xFFFF).astype(np.uint64).sum()) & 0xFFFFFFFF,
+                  np.uint32(v.view(np.int32).min()), np.uint32(v.view(np.int32).max()),
+                  np.bitwise_and.reduce(v), np.bitwise_or.reduce(v), np.bitwise_xor.reduce(v)]
+    return m, rank.reshape(-1), mm.reshape(-1), rec
+
+
+@pytest.mark.parametrize("D", (0, 1, 102, 512, 922, 1024))
+def test_dynamic_groups_plain_definitions(oracle_mod, D):
+    x = inputs.masked_input(32 * 997)
+    mm, rank, rec, filt, cnt = oracle_mod.warp_dynamic(x, D)
+    m, wrank, wmm, wrec = _dyn_plain(x, D)
+    assert np.array_equal(rank, wrank) and np.array_equal(mm, wmm) and np.array_equal(rec, wrec)
+    members = (x.view(np.uint32) & 1023) < D
+    assert cnt == int(members.sum()) == sum(bin(int(v)).count("1") for v in m)
+    # the append: every warp's members, contiguous and in rank order
+    assert np.array_equal(np.sort(filt), np.sort(x[members]))
+    xs, ps = x.reshape(-1, 32), members.reshape(-1, 32)
+    pos = {}
+    for g in range(xs.shape[0]):
+        run = xs[g][ps[g]]
+        if run.size:
+            hits = np.flatnonzero(filt == run[0])
+            assert any(np.array_equal(filt[h:h + run.size], run) for h in hits)
+
+
+def test_dynamic_groups_special_cases(oracle_mod):
+    # every key equal inside a warp: match_all returns the mask, match_any
+    # the whole mask for every member
+    x = (np.arange(32 * 32, dtype=np.int64) | (5 << 10)).astype(np.int32)
+    mm, rank, rec, filt, cnt = oracle_mod.warp_dynamic(x, 512)
+    p = (x.view(np.uint32) & 1023) < 512
+    m = rec[:, 0]
+    # low bits 32g + l: warps 0..15 are all members, warps 16..31 have none
+    assert np.array_equal(rec[:, 1], m) and np.all(m[:16] == 0xFFFFFFFF) and np.all(rec[16:] == 0)
+    assert np.array_equal(mm[p], np.repeat(m, 32)[p])
+    assert cnt == p.sum()
+    # one member: reductions are its own value, rank 0, match set itself
+    x = np.full(32, 1023, np.int32)
+    x[7] = 5 | (3 << 10)
+    mm, rank, rec, filt, cnt = oracle_mod.warp_dynamic(x, 512)
+    assert rec[0].tolist() == [1 << 7, 1 << 7, int(x[7]) & 0xFFFF, x[7], x[7], x[7], x[7], x[7]]
+    assert rank[7] == 0 and mm[7] == 1 << 7 and cnt == 1 and filt[0] == x[7]
