@@ -113,7 +113,8 @@ def _entry(n, nbytes, ms):
 def other_kernels(fg, reps=10):
     """The kernels outside the timed step, each timed on its own: the
     block reduce (2^20 int32), the masked warp operations at three
-    densities and the tile reductions (2^26 int32), and the precision
+    densities, the dynamic groups and the tile reductions (2^26 int32),
+    and the precision
     variants over 2^28 elements (float32 and bfloat16, sum and dot, plain
     and TwoSum).  Their timing does not depend on the values, so the
     precision variants run on the primitive set's float32 N(0, 1) array, a
@@ -134,6 +135,14 @@ def other_kernels(fg, reps=10):
     for D in inputs.MASK_DENSITIES:
         res[f"masked_d{D}_2p26"] = _entry(nm, 8 * nm + 16 * (nm // 32),
                                           _timed(lambda: cox.warp_masked(xm, D, out, rec), reps))
+    mm_, rk_, rc_ = torch.empty_like(xm), torch.empty_like(xm), torch.empty((nm // 32, 8), dtype=torch.int32,
+                                                                            device="cuda")
+    fl_, fc_ = torch.empty_like(xm), torch.empty(1, dtype=torch.int64, device="cuda")
+    members = int((((xm.view(torch.int32) & 1023) < 512)).sum().item())
+    res["dynamic_groups_d512_2p26"] = _entry(
+        nm, 12 * nm + 32 * (nm // 32) + 4 * members,
+        _timed(lambda: cox.warp_dynamic(xm, 512, mm_, rk_, rc_, fl_, fc_), reps))
+    del mm_, rk_, rc_, fl_, fc_
     for T in inputs.TILE_SIZES:
         to = torch.empty(nm // T, dtype=torch.int32, device="cuda")
         res[f"tile_reduce_t{T}_2p26"] = _entry(nm, 4 * nm + 4 * (nm // T),

@@ -240,6 +240,32 @@ cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, 
 cox_status cox_warp_masked(const int32_t *x, int64_t n, int density, int32_t *out, uint32_t *rec,
                            void *stream);
 
+/* Dynamic groups (the dynamic cooperative group of the filter kernel that
+ * COX does not support, Table 1; cooperative groups, section 2.2.2;
+ * static-only limitation, section 2.2.3), n % 32 == 0.  Lane l of warp g,
+ * x = x[32g + l]:
+ *   p = ((uint32)x & 1023) < density;
+ *   if (p) { grp = coalesced_threads();  m = __activemask();
+ *            rank[e] = grp.thread_rank();  key = ((uint32)x >> 10) & 7;
+ *            match_any[e] = __match_any_sync(m, key);
+ *            ma = __match_all_sync(m, key, &pred);
+ *            add = __reduce_add_sync(m, x & 0xffff);  min / max =
+ *            __reduce_min_sync / __reduce_max_sync(m, x) (signed);
+ *            and / or / xor = __reduce_{and,or,xor}_sync(m, (unsigned) x);
+ *            the rank-0 member appends grp.size() slots to filtered[] and
+ *            shares the base (grp.shfl); filtered[base + rank] = x;
+ *            the rank-0 member stores rec[g] = {m, ma, add, min, max, and,
+ *            or, xor} }
+ *   else { match_any[e] = 0; rank[e] = 0xffffffff; }
+ *   (m == 0: rec[g] = 8 zeros).
+ * *filtered_count (device int64) = number of members.  Every warp's
+ * members occupy consecutive slots of filtered[] in rank order; the order
+ * of the warps' runs is the order their appends happen to take (not
+ * deterministic).  x, match_any, rank: [n]; rec: uint32[8 * n/32], 16-byte
+ * aligned; filtered: int32[n] capacity. */
+cox_status cox_warp_dynamic(const int32_t *x, int64_t n, int density, uint32_t *match_any, uint32_t *rank,
+                            uint32_t *rec, int32_t *filtered, int64_t *filtered_count, void *stream);
+
 /* ---------------------------------------------------------------------
  * Segmented batching: thousands of uneven CSR segments in one persistent
  * launch.  The paper runs one CUDA block per CPU thread through pthread

@@ -60,6 +60,7 @@ _SIGS = {
     "cox_tile_sort": (_I, [_P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
     "cox_tile_reduce": (_I, [_P, _I64, _I, _P, _P]),
     "cox_warp_masked": (_I, [_P, _I64, _I, _P, _P, _P]),
+    "cox_warp_dynamic": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
     "cox_segmented": (_I, [_P, _I, _P, _I64, _I64, _P, _P, _P, _P, _I, C.POINTER(cox_cfg), _P, _SZ, _P]),
     "cox_segmented_reduce": (_I, [_P, _I, _P, _I64, _I64, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
     "cox_segmented_scan": (_I, [_P, _I, _P, _I64, _I64, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
@@ -321,6 +322,24 @@ def warp_masked(x, density, out=None, rec=None):
     _check(lib().cox_warp_masked(_ptr(x), n, int(density), _ptr(out), _ptr(rec), _stream()),
            "cox_warp_masked")
     return out, rec
+
+
+def warp_dynamic(x, density, match_any=None, rank=None, rec=None, filtered=None, count=None):
+    """Dynamic groups (coalesced_threads, match_any / match_all, the six
+    reduce_*_sync, warp-aggregated append).  Returns (match_any, rank,
+    rec[n/32, 8], filtered (capacity n), count as a 1-element int64 device
+    tensor); the members are filtered[:count]."""
+    _need(x, torch.int32, "x")
+    n = x.numel()
+    dev = x.device
+    match_any = torch.empty(n, dtype=torch.int32, device=dev) if match_any is None else match_any
+    rank = torch.empty(n, dtype=torch.int32, device=dev) if rank is None else rank
+    rec = torch.empty((n // 32, 8), dtype=torch.int32, device=dev) if rec is None else rec
+    filtered = torch.empty_like(x) if filtered is None else filtered
+    count = torch.empty(1, dtype=torch.int64, device=dev) if count is None else count
+    _check(lib().cox_warp_dynamic(_ptr(x), n, int(density), _ptr(match_any), _ptr(rank), _ptr(rec), _ptr(filtered),
+                                  _ptr(count), _stream()), "cox_warp_dynamic")
+    return match_any, rank, rec, filtered, count
 
 
 def stream_read(x, sink=None, grid_blocks=0):
