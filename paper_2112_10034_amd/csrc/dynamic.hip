@@ -4,16 +4,20 @@
 // which COX could not run: its Table 1; Sec. 2.2.2-2.2.3 for the groups).
 //
 // One element per lane (element e: logical lane e & 31 of logical warp
-// e >> 5), rows of 1024 consecutive elements, R rows per round.  Per row:
+// e >> 5), rows of blockDim consecutive elements, R rows per round.  Per
+// row:
 //   p = ((uint32)x & 1023) < D; the members m of a logical warp are the
 //   lanes with p (the group coalesced_threads() returns inside `if (p)`);
 //   rank = popc(m & lanemask_lt) (mbcnt over the wave's 64-bit ballot);
-//   match_any(m, key): the wave walks the distinct (half, key) classes of
-//   its members -- a leader's key by v_readlane, one 64-bit ballot per
-//   class -- so any 32-bit operand works, in one step per distinct value;
+//   the six reductions: all-reduce inside each 16-lane row by DPP row
+//   rotations (8, 4, 2, 1) fused into the ALU op, then one row swap
+//   (v_permlane16_swap); lanes outside m hold the operation's identity;
+//   match_any(m, key): m intersected, for every key bit on which the
+//   members differ, with the members agreeing with the lane on that bit
+//   (one ballot per bit) -- one step per varying bit.  The key is bits
+//   10..12 of x, so the bits on which the members differ are those of
+//   (OR ^ AND) of x over the members, already reduced;
 //   match_all: a member's match set is the whole mask;
-//   the six reductions: xor butterflies inside the 32-lane half with the
-//   operation's identity for lanes outside m;
 //   append: the rank-0 member takes the group's slots from a block
 //   counter in shared memory, the members read the base from it (a
 //   shuffle from the rank-0 lane); once per round one global atomic turns
@@ -24,13 +28,19 @@
 
 namespace cox {
 
-template <int M>
-__device__ __forceinline__ uint32_t xl(uint32_t v) {
-  return (uint32_t)xor_lane<M>((int)v);
+// all-reduce of v over the logical warp's 32 lanes for a commutative op
+// (every lane ends with the result): rotations inside the 16-lane rows,
+// then v_permlane16_swap of v with itself, which leaves every lane its own
+// row's value and the other row's, in one order or the other
+template <class F>
+__device__ __forceinline__ uint32_t allreduce32(uint32_t v, F op) {
+  v = op(v, (uint32_t)dpp_mov<0x128>((int)v));  // row_ror:8
+  v = op(v, (uint32_t)dpp_mov<0x124>((int)v));  // row_ror:4
+  v = op(v, (uint32_t)dpp_mov<0x122>((int)v));  // row_ror:2
+  v = op(v, (uint32_t)dpp_mov<0x121>((int)v));  // row_ror:1
+  const auto pr = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return op((uint32_t)pr[0], (uint32_t)pr[1]);
 }
-
-__device__ __forceinline__ int32_t imin(int32_t a, int32_t b) { return a < b ? a : b; }
-__device__ __forceinline__ int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
 
 template <int R>
 __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict__ x, int64_t n, int D,
@@ -39,7 +49,7 @@ __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict
                                                       unsigned long long *__restrict__ counter) {
   __shared__ uint32_t s_cnt;
   __shared__ unsigned long long s_base;
-  const int t = threadIdx.x, l = t & 31, t64 = t & 63;
+  const int t = threadIdx.x, l = t & 31;
   const bool hi = (t & 32) != 0;
   const uint64_t my_half = hi ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
   const uint32_t lt = l ? (0xFFFFFFFFu >> (32 - l)) : 0u;
@@ -51,7 +61,8 @@ __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict
   for (int64_t it = 0; it < rounds; it++) {
     const int64_t base = it * stride + (int64_t)blockIdx.x * per_block;
     int32_t xs[R];
-    uint32_t wb[R], rk[R];
+    // a member's slot in the block's range (< 2^15), two rows per register
+    uint32_t pos2[R / 2];
     uint32_t pbits = 0u;  // bit r: member in row r
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -69,42 +80,41 @@ __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict
       const uint32_t m = (uint32_t)((P & my_half) >> (hi ? 32 : 0));
       const uint32_t rank = (uint32_t)__builtin_popcount(m & lt);
       const uint32_t key = ((uint32_t)xv >> 10) & 7u;
-      // match_any: one ballot per distinct (half, key) class of members
-      uint32_t mm = 0u;
-      uint64_t rem = P;
-      while (rem) {
-        const int ld = __builtin_ctzll(rem);
-        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, ld);
-        const uint64_t cls = __builtin_amdgcn_ballot_w64(key == k) & P &
-                             (ld < 32 ? 0x00000000FFFFFFFFull : 0xFFFFFFFF00000000ull);
-        if ((cls >> t64) & 1ull) mm = (uint32_t)((cls & my_half) >> (hi ? 32 : 0));
-        rem &= ~cls;
+      // reductions over the members of the warp (identity elsewhere)
+      const auto add = [](uint32_t a, uint32_t b) { return a + b; };
+      const auto mn = [](uint32_t a, uint32_t b) { return (int32_t)a < (int32_t)b ? a : b; };
+      const auto mx = [](uint32_t a, uint32_t b) { return (int32_t)a > (int32_t)b ? a : b; };
+      const auto band = [](uint32_t a, uint32_t b) { return a & b; };
+      const auto bor = [](uint32_t a, uint32_t b) { return a | b; };
+      const auto bxor = [](uint32_t a, uint32_t b) { return a ^ b; };
+      const uint32_t ra = allreduce32(p ? ((uint32_t)xv & 0xFFFFu) : 0u, add);
+      const uint32_t rmn = allreduce32(p ? (uint32_t)xv : (uint32_t)INT32_MAX, mn);
+      const uint32_t rmx = allreduce32(p ? (uint32_t)xv : (uint32_t)INT32_MIN, mx);
+      const uint32_t rnd = allreduce32(p ? (uint32_t)xv : 0xFFFFFFFFu, band);
+      const uint32_t rr = allreduce32(p ? (uint32_t)xv : 0u, bor);
+      const uint32_t rx = allreduce32(p ? (uint32_t)xv : 0u, bxor);
+      // match_any: m narrowed by one agreement ballot per key bit on which
+      // the wave's members differ
+      const uint32_t kvary = ((rr ^ rnd) >> 10) & 7u;
+      uint32_t vary = (uint32_t)__builtin_amdgcn_readlane((int)kvary, 0) |
+                      (uint32_t)__builtin_amdgcn_readlane((int)kvary, 32);
+      uint32_t mm = m;
+      while (vary) {
+        const int b = __builtin_ctz(vary);
+        const bool bit = (key >> b) & 1u;
+        const uint64_t B = __builtin_amdgcn_ballot_w64(bit);
+        const uint32_t Bh = (uint32_t)((B & my_half) >> (hi ? 32 : 0));
+        mm &= bit ? Bh : ~Bh;
+        vary &= vary - 1u;
       }
       const uint32_t ma = (p && mm == m) ? m : 0u;
-      // reductions over the members of the half
-      uint32_t ra = p ? ((uint32_t)xv & 0xFFFFu) : 0u;
-      int32_t rmn = p ? xv : INT32_MAX, rmx = p ? xv : INT32_MIN;
-      uint32_t rnd = p ? (uint32_t)xv : 0xFFFFFFFFu, rr = p ? (uint32_t)xv : 0u, rx = rr;
-#define COX_DYN_STEP(M)                                                   \
-  ra += xl<M>(ra);                                                        \
-  rmn = imin(rmn, (int32_t)xl<M>((uint32_t)rmn));                         \
-  rmx = imax(rmx, (int32_t)xl<M>((uint32_t)rmx));                         \
-  rnd &= xl<M>(rnd);                                                      \
-  rr |= xl<M>(rr);                                                        \
-  rx ^= xl<M>(rx);
-      COX_DYN_STEP(16)
-      COX_DYN_STEP(8)
-      COX_DYN_STEP(4)
-      COX_DYN_STEP(2)
-      COX_DYN_STEP(1)
-#undef COX_DYN_STEP
       // the warp's record, from its rank-0 member (lane 0 if m is empty)
       const int wl = m ? __builtin_ctz(m) : 0;
       if (in && l == wl) {
         uint4 *dst = (uint4 *)(rec + 8 * (e >> 5));
         if (m) {
-          dst[0] = make_uint4(m, ma, ra, (uint32_t)rmn);
-          dst[1] = make_uint4((uint32_t)rmx, rnd, rr, rx);
+          dst[0] = make_uint4(m, ma, ra, rmn);
+          dst[1] = make_uint4(rmx, rnd, rr, rx);
         } else {
           dst[0] = make_uint4(0u, 0u, 0u, 0u);
           dst[1] = make_uint4(0u, 0u, 0u, 0u);
@@ -113,8 +123,9 @@ __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict
       // warp-aggregated append: the group's slots in the block's range
       uint32_t slot = 0u;
       if (p && rank == 0u) slot = atomicAdd(&s_cnt, (uint32_t)__builtin_popcount(m));
-      wb[r] = (uint32_t)bperm((int)slot, (hi ? 32 : 0) + wl);
-      rk[r] = rank;
+      const uint32_t pos = (uint32_t)bperm((int)slot, (hi ? 32 : 0) + wl) + rank;
+      if (r & 1) pos2[r / 2] |= pos << 16;
+      else pos2[r / 2] = pos;
       pbits |= p ? (1u << r) : 0u;
       if (in) {
         mm_out[e] = p ? mm : 0u;
@@ -130,7 +141,7 @@ __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict
     const unsigned long long gb = s_base;
 #pragma unroll
     for (int r = 0; r < R; r++)
-      if ((pbits >> r) & 1u) filt[gb + wb[r] + rk[r]] = xs[r];
+      if ((pbits >> r) & 1u) filt[gb + ((pos2[r / 2] >> (16 * (r & 1))) & 0xFFFFu)] = xs[r];
     // s_base is rewritten only after the next round's first barrier
   }
 }
@@ -153,9 +164,10 @@ cox_status cox_warp_dynamic(const int32_t *x, int64_t n, int density, uint32_t *
   if (st != COX_OK || n == 0) return st;
   if (!x || !match_any || !rank || !rec || !filtered) return COX_ERR_INVALID;
   if (!aligned16(rec)) return COX_ERR_ALIGN;
+  // 512-thread blocks: three per compute unit at this kernel's registers
   auto fn = k_warp_dynamic<16>;
-  const int grid = persistent_grid((const void *)fn, 1024, (n + 1024 * 16 - 1) / (1024 * 16), 0, 0, 2);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(1024), 0, (hipStream_t)stream, x, n, density, match_any, rank, rec,
+  const int grid = persistent_grid((const void *)fn, 512, (n + 512 * 16 - 1) / (512 * 16), 0, 0, 4);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(512), 0, (hipStream_t)stream, x, n, density, match_any, rank, rec,
                      filtered, (unsigned long long *)filtered_count);
   return launch_status();
 }
