@@ -107,7 +107,7 @@ def _timed(fn, reps):
 def _entry(n, nbytes, ms):
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2), "gb_s": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": int(nbytes)}
 
 
 def other_kernels(fg, reps=10):
@@ -351,7 +351,8 @@ def main():
         ms = per[nm]
         gbs = alg_bytes[nm] / (ms * 1e-3) / 1e9
         kernels[nm] = {"ms": round(ms, 4), "gelem_s": round(n / (ms * 1e-3) / 1e9, 2),
-                       "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                       "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+                       "algorithmic_bytes": int(alg_bytes[nm])}
     dom = max(names, key=lambda k: per[k])
     achieved = alg_bytes[dom] / (per[dom] * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
