@@ -241,6 +241,29 @@ def test_tile_sort_adversarial_and_zero_one(dev):
             assert np.array_equal(got, np.sort(c.reshape(-1, 32), axis=1).reshape(-1))
 
 
+@pytest.mark.parametrize("k", [4, 1])
+def test_tile_sort_all_zero_one_groups(dev, k):
+    """The 0-1 principle (Knuth, TAOCP vol. 3, 5.3.4): a comparator network
+    sorts every input iff it sorts every 0/1 input.  All 2^32 0/1 patterns
+    of a 32-key group go through the GPU network, 2^24 patterns per launch;
+    a sorted 0/1 group is (32 - c) zeros then c ones, c = its popcount."""
+    torch, cox = dev
+    per = 1 << 24
+    lanes = torch.arange(32, device="cuda", dtype=torch.int64)
+    out = torch.empty(per * 32, dtype=torch.int32, device="cuda")
+    for b in range((1 << 32) // per):
+        pat = torch.arange(b * per, (b + 1) * per, device="cuda", dtype=torch.int64)
+        keys = ((pat[:, None] >> lanes) & 1).to(torch.int32).reshape(-1)
+        cox.tile_sort(keys, cfg=(k, 0), out=out)
+        ones = keys.view(-1, 32).sum(1, keepdim=True)
+        want = (lanes[None, :] >= 32 - ones).to(torch.int32)
+        if not torch.equal(out.view(-1, 32), want):
+            bad = int((out.view(-1, 32) != want).any(1).nonzero()[0, 0])
+            raise AssertionError(f"pattern {b * per + bad:#010x} not sorted")
+        del keys, ones, want, pat
+    print("all 2^32 zero-one groups sorted, keys per lane", k, flush=True)
+
+
 # ---------------------------------------------------------------- tile reduce / masked
 @pytest.mark.parametrize("T", [2, 4, 8, 16, 32])
 @pytest.mark.parametrize("n", [1, 7, 256 * 8 * 5 + 37, 4096 * 700 + 4093])
