@@ -72,6 +72,8 @@ def lib():
             "coxo_two_prod": (None, [C.c_float, C.c_float, P, P]),
             "coxo_code5": (I, [P, P, P, P, I]),
             "coxo_uniform_branch": (I, [P, P, I64, P]),
+            "coxo_grid_exchange": (I, [I, I, I, P]),
+            "coxo_cg": (I, [P, P, P, I64, P, P, I, C.c_double, I, I, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -262,6 +264,36 @@ def segmented(x, offsets, k, W):
     _check(lib().coxo_segmented(_p(x), dt, _p(off), nseg, k, W, _p(tot), _p(y), _p(oc), _p(cnt)),
            "segmented")
     return tot, y, oc, cnt
+
+
+def grid_exchange(G, rounds, block=1024):
+    """Exchange kernel with grid barriers: per round every block publishes
+    a row of mixed values, and after a grid barrier reads the row of block
+    (b + r + 1) % G.  Returns the per-thread sums, uint32[G, block]."""
+    out = np.zeros(G * block, np.uint32)
+    _check(lib().coxo_grid_exchange(G, block, rounds, _p(out)), "grid_exchange")
+    return out.reshape(G, block)
+
+
+CG_CONVERGED, CG_MAX_ITER, CG_BREAKDOWN = 0, 1, 2
+
+
+def cg(row_ptr, col_idx, val, b, x0, max_iter, tol, R, W):
+    """Conjugate gradient on the CSR matrix (row_ptr, col_idx, val) with the
+    inner-product schedule (R, W).  Returns (x, iterations, reason,
+    rr_hist[: iterations + 1])."""
+    rp = _c(row_ptr, np.int32)
+    ci = _c(col_idx, np.int32)
+    va = _c(val, np.float32)
+    bb = _c(b, np.float32)
+    x = np.array(x0, dtype=np.float32, copy=True)
+    n = bb.size
+    res = np.zeros(2, np.int32)
+    hist = np.zeros(max_iter + 1, np.float64)
+    _check(lib().coxo_cg(_p(rp), _p(ci), _p(va), n, _p(bb), _p(x), int(max_iter), float(tol), R, W,
+                         _p(res), _p(hist)), "cg")
+    k = int(res[0])
+    return x, k, int(res[1]), hist[: k + 1]
 
 
 def exact_sum(x, y=None):

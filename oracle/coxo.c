@@ -1736,3 +1736,230 @@ int coxo_uniform_branch(const int32_t *cond, const int32_t *x, int64_t n, int32_
   ub_ctx c = {cond, x, out};
   return run_blocks(n / 32, ub_block, &c);
 }
+
+/* ================================================================== */
+/* grid-wide barriers (this_grid().sync(), Sec. 2.2.2; COX could not run */
+/* kernels that need one, Sec. 5.1 and Table 1)                         */
+/*                                                                      */
+/* A grid barrier is collapsed one level above the block barrier of     */
+/* Sec. 3.5: the kernel is split at it into grid-level regions, and a   */
+/* region runs for every block before the next one starts.  Here every  */
+/* grid-level region is one run_blocks pass.                            */
+/* ================================================================== */
+
+/* MurmurHash3's 32-bit finaliser (Appleby), the payload mixer of the    */
+/* exchange kernel                                                       */
+static uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+/* Exchange kernel: G blocks of BT threads, `rounds` rounds; in round r
+ *   region 1: thread t of block b writes fmix32(r << 20 ^ b << 10 ^ t) to
+ *             slot[b][t];
+ *   grid barrier;
+ *   region 2: thread t of block b adds (mod 2^32) slot[(b + r + 1) % G][t]
+ *             to its sum;
+ *   grid barrier (the next round overwrites the slots).
+ * out[b * BT + t] = the sum. */
+typedef struct {
+  int G, BT, r;
+  uint32_t *slot, *out;
+} gx_ctx;
+
+static void gx_write(void *p, int64_t b) {
+  gx_ctx *c = (gx_ctx *)p;
+  for (int t = 0; t < c->BT; t++)
+    c->slot[b * c->BT + t] = fmix32(((uint32_t)c->r << 20) ^ ((uint32_t)b << 10) ^ (uint32_t)t);
+}
+static void gx_read(void *p, int64_t b) {
+  gx_ctx *c = (gx_ctx *)p;
+  const int64_t src = (b + c->r + 1) % c->G;
+  for (int t = 0; t < c->BT; t++) c->out[b * c->BT + t] += c->slot[src * c->BT + t];
+}
+
+int coxo_grid_exchange(int G, int BT, int rounds, uint32_t *out) {
+  if (G < 1 || G > 1024 || BT < 1 || BT > 1024 || rounds < 0) return COXO_ERR_INVALID;
+  uint32_t *slot = (uint32_t *)calloc((size_t)G * BT, 4);
+  if (!slot) return COXO_ERR_NOMEM;
+  memset(out, 0, (size_t)G * BT * 4);
+  gx_ctx c = {G, BT, 0, slot, out};
+  int st = COXO_OK;
+  for (int r = 0; r < rounds && st == COXO_OK; r++) {
+    c.r = r;
+    st = run_blocks(G, gx_write, &c);
+    if (st == COXO_OK) st = run_blocks(G, gx_read, &c);
+  }
+  free(slot);
+  return st;
+}
+
+/* ------------------------------------------------------------------ */
+/* Conjugate gradient (Hestenes and Stiefel, 1952) for a symmetric       */
+/* positive definite A in CSR form: the solver of gpuConjugateGradient   */
+/* (Table 1), whose iterations are separated by grid barriers.           */
+/* Vectors are binary32, scalars binary64:                                */
+/*   r = b - A x;  rr_0 = <r, r>                                          */
+/*   for k = 0, 1, ...:                                                    */
+/*     stop (reason 0) if rr_k <= tol^2, (reason 1) if k == max_iter       */
+/*     p = r if k == 0, else fmaf(beta, p, r), beta = (float)(rr_k/rr_k-1) */
+/*     q = A p;  pq = <p, q>;  stop (reason 2) unless pq > 0               */
+/*     alpha = (float)(rr_k / pq)                                          */
+/*     x = fmaf(alpha, p, x);  r = fmaf(-alpha, q, r);  rr_k+1 = <r, r>    */
+/* (A v)_i = the row's entries in storage order accumulated from +0.0f as */
+/* acc = fmaf(a_ij, v_j, acc).                                             */
+/* <u, v> with schedule (R, W): chunk c is rows [cS, cS + S), S = 32 W R;  */
+/* thread (w, l) adds the exact products (double) u_i * (double) v_i of    */
+/* rows cS + 32 W q + 32 w + l, q = 0 .. R-1 (rows past n add nothing), in */
+/* FP64 from -0.0; each warp runs the shfl_down tree, warp 0 runs it over  */
+/* the W warp values (-0.0 beyond W): the chunk value; final_f64 combines  */
+/* the chunk values.  Every grid-level region below is one pass.           */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  const int32_t *rp, *ci;
+  const float *val, *b;
+  float *x, *r, *p, *q;
+  int64_t n, S;
+  int R, W;
+  float coef;   /* beta of the p pass, alpha of the x/r pass */
+  int first;    /* p pass of iteration 0 */
+  double *part; /* chunk values of the pass's inner product */
+} cg_ctx;
+
+static float cg_row(const cg_ctx *g, int64_t i, const float *v) {
+  float acc = 0.0f;
+  for (int64_t jj = g->rp[i]; jj < g->rp[i + 1]; jj++) acc = fmaf(g->val[jj], v[g->ci[jj]], acc);
+  return acc;
+}
+
+static void tree_f64_shfl_down(double *a, xch_t *X) {
+  for (int o = 16; o > 0; o >>= 1) {
+    for (int l = 0; l < 32; l++) xch_put(X, l, dbits(a[l]));
+    for (int l = 0; l < 32; l++) a[l] = a[l] + bitsd(wf_shfl(X, l, FULL, SH_DOWN, o, 32));
+    xch_war(X);
+  }
+}
+
+/* the chunk value of <u, v> */
+static double cg_chunk_dot(const cg_ctx *g, int64_t c, const float *u, const float *v) {
+  const int W = g->W, R = g->R;
+  double t[32 * MAXW];
+  double slot[MAXW];
+  xch_t X;
+  xch_war(&X);
+  for (int w = 0; w < W; w++) {
+    for (int l = 0; l < 32; l++) {
+      double s = -0.0;
+      for (int q = 0; q < R; q++) {
+        const int64_t i = c * g->S + (int64_t)32 * W * q + 32 * w + l;
+        if (i < g->n) s = s + (double)u[i] * (double)v[i];
+      }
+      t[32 * w + l] = s;
+    }
+    tree_f64_shfl_down(&t[32 * w], &X);
+    slot[w] = t[32 * w];
+  }
+  double a[32];
+  for (int l = 0; l < 32; l++) a[l] = l < W ? slot[l] : -0.0;
+  tree_f64_shfl_down(a, &X);
+  return a[0];
+}
+
+static int64_t cg_lo(const cg_ctx *g, int64_t c) { return c * g->S; }
+static int64_t cg_hi(const cg_ctx *g, int64_t c) {
+  const int64_t e = (c + 1) * g->S;
+  return e < g->n ? e : g->n;
+}
+
+/* r = b - A x, chunk values of <r, r> */
+static void cg_pass_r0(void *p, int64_t c) {
+  cg_ctx *g = (cg_ctx *)p;
+  for (int64_t i = cg_lo(g, c); i < cg_hi(g, c); i++) g->r[i] = g->b[i] - cg_row(g, i, g->x);
+  g->part[c] = cg_chunk_dot(g, c, g->r, g->r);
+}
+/* p = r or fmaf(beta, p, r) */
+static void cg_pass_p(void *p, int64_t c) {
+  cg_ctx *g = (cg_ctx *)p;
+  for (int64_t i = cg_lo(g, c); i < cg_hi(g, c); i++) g->p[i] = g->first ? g->r[i] : fmaf(g->coef, g->p[i], g->r[i]);
+}
+/* q = A p, chunk values of <p, q> */
+static void cg_pass_q(void *p, int64_t c) {
+  cg_ctx *g = (cg_ctx *)p;
+  for (int64_t i = cg_lo(g, c); i < cg_hi(g, c); i++) g->q[i] = cg_row(g, i, g->p);
+  g->part[c] = cg_chunk_dot(g, c, g->p, g->q);
+}
+/* x += alpha p, r -= alpha q, chunk values of <r, r> */
+static void cg_pass_xr(void *p, int64_t c) {
+  cg_ctx *g = (cg_ctx *)p;
+  for (int64_t i = cg_lo(g, c); i < cg_hi(g, c); i++) {
+    g->x[i] = fmaf(g->coef, g->p[i], g->x[i]);
+    g->r[i] = fmaf(-g->coef, g->q[i], g->r[i]);
+  }
+  g->part[c] = cg_chunk_dot(g, c, g->r, g->r);
+}
+
+/* rp: int32[n+1] with rp[0] = 0, nondecreasing, rp[n] = nnz; ci: int32[nnz]
+ * column indices in [0, n); val: float[nnz]; b: float[n]; x: float[n], the
+ * start on entry and the result on return.  result[0] = iterations k,
+ * result[1] = reason; rr_hist[0 .. k] = rr_0 .. rr_k (max_iter + 1
+ * entries). */
+int coxo_cg(const int32_t *rp, const int32_t *ci, const float *val, int64_t n, const float *b, float *x,
+            int max_iter, double tol, int R, int W, int32_t *result, double *rr_hist) {
+  if (n < 0 || max_iter < 0 || !sigma_ok(R, W) || R > 8) return COXO_ERR_INVALID;
+  if (n > 0 && rp[0] != 0) return COXO_ERR_INVALID;
+  for (int64_t i = 0; i < n; i++) {
+    if (rp[i + 1] < rp[i]) return COXO_ERR_INVALID;
+    for (int64_t jj = rp[i]; jj < rp[i + 1]; jj++)
+      if (ci[jj] < 0 || ci[jj] >= n) return COXO_ERR_INVALID;
+  }
+  const int64_t S = (int64_t)32 * W * R;
+  const int64_t nch = (n + S - 1) / S;
+  const size_t nb = (size_t)(n > 0 ? n : 1) * sizeof(float);
+  float *r = (float *)malloc(nb), *pv = (float *)malloc(nb), *q = (float *)malloc(nb);
+  double *part = (double *)malloc((size_t)(nch > 0 ? nch : 1) * sizeof(double));
+  int st = COXO_OK;
+  if (!r || !pv || !q || !part) st = COXO_ERR_NOMEM;
+  cg_ctx g = {rp, ci, val, b, x, r, pv, q, n, S, R, W, 0.0f, 1, part};
+  const double tol2 = tol * tol;
+  int k = 0, reason = 0;
+  double rr = 0.0, rr_prev = 0.0;
+  if (st == COXO_OK) st = run_blocks(nch, cg_pass_r0, &g);
+  if (st == COXO_OK) rr = final_f64(part, nch);
+  for (; st == COXO_OK; k++) {
+    rr_hist[k] = rr;
+    if (rr <= tol2) {
+      reason = 0;
+      break;
+    }
+    if (k == max_iter) {
+      reason = 1;
+      break;
+    }
+    g.first = k == 0;
+    g.coef = k == 0 ? 0.0f : (float)(rr / rr_prev);
+    st = run_blocks(nch, cg_pass_p, &g);
+    if (st == COXO_OK) st = run_blocks(nch, cg_pass_q, &g);
+    if (st != COXO_OK) break;
+    const double pq = final_f64(part, nch);
+    if (!(pq > 0.0)) {
+      reason = 2;
+      break;
+    }
+    g.coef = (float)(rr / pq);
+    st = run_blocks(nch, cg_pass_xr, &g);
+    if (st != COXO_OK) break;
+    rr_prev = rr;
+    rr = final_f64(part, nch);
+  }
+  result[0] = k;
+  result[1] = reason;
+  free(r);
+  free(pv);
+  free(q);
+  free(part);
+  return st;
+}

@@ -20,12 +20,24 @@ so tests can draw smaller instances from the same recipe):
    sum|x| / |sum x| is about 1e8; n = 2^28.
 4. segments: 10,000 segment lengths min(round(lognormal(ln 2000, 1.97)),
    2^20); int32 uniform in [-2^20, 2^20] and float32 N(0, 1) values.
+5. conjugate gradient systems (CSR, float32 values, columns ascending in
+   each row):
+   - tridiagonal: off-diagonal pairs a(i, i+1) = a(i+1, i) = -U[0, 1),
+     diagonal 3 + U[0, 1) (strictly diagonally dominant, hence positive
+     definite, eigenvalues in (1, 6)); right-hand side U[-1, 1); n = 2^20
+     rows (the size of the CUDA sample's system) and 2^24;
+   - irregular: about n * deg / 2 off-diagonal pairs (i, j), i != j, with i
+     drawn as floor(n * U^2) (so low rows are long) and j uniform, value
+     -U[0, 1) mirrored to (j, i) (duplicate pairs stay as separate
+     entries); diagonal 1 + U[0, 1) + the row's sum of |off-diagonal|;
+     right-hand side U[-1, 1).
 """
 import numpy as np
 
 BASE_SEED = 2112100340
 
 FULL_N = {0: 1 << 20, 1: 1 << 28, 2: 1 << 26, 3: 1 << 28}
+CG_N = (1 << 20, 1 << 24)
 NSEG = 10_000
 SEG_MEDIAN = 2000
 SEG_SIGMA = 1.97
@@ -232,3 +244,48 @@ def segment_values(total, seed=None):
     x = g_i.integers(-(1 << 20), (1 << 20) + 1, size=total, dtype=np.int32)
     f = g_f.standard_normal(size=total, dtype=np.float32)
     return x, f
+
+
+def _csr(rows, cols, vals, n):
+    order = np.lexsort((cols, rows))
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    return rp, cols[order].astype(np.int32), vals[order].astype(np.float32)
+
+
+def cg_tridiag(n, seed=None):
+    """(row_ptr, col_idx, val, b) of the tridiagonal system of workload 5."""
+    g_off, g_diag, g_b = _streams(5, 3, seed)
+    u = g_off.random(size=max(n - 1, 0), dtype=np.float32)
+    d = np.float32(3) + g_diag.random(size=n, dtype=np.float32)
+    b = g_b.random(size=n, dtype=np.float32) * np.float32(2) - np.float32(1)
+    i = np.arange(n, dtype=np.int64)
+    cols = np.stack([i - 1, i, i + 1], axis=1)
+    vals = np.zeros((n, 3), np.float32)
+    vals[1:, 0] = -u
+    vals[:, 1] = d
+    vals[:-1, 2] = -u
+    valid = (cols >= 0) & (cols < n)
+    rp = np.zeros(n + 1, np.int32)
+    np.cumsum(valid.sum(axis=1), out=rp[1:])
+    return rp, cols[valid].astype(np.int32), vals[valid], b
+
+
+def cg_irregular(n, deg=6, seed=None):
+    """(row_ptr, col_idx, val, b) of the irregular system of workload 5."""
+    g_i, g_j, g_v, g_d, g_b = _streams(5, 5, None if seed is None else seed + 1)
+    m = n * deg // 2
+    i = np.floor(n * g_i.random(size=m) ** 2).astype(np.int64)
+    j = g_j.integers(0, n, size=m, dtype=np.int64)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    v = -g_v.random(size=i.size, dtype=np.float32)
+    rows = np.concatenate([i, j, np.arange(n, dtype=np.int64)])
+    cols = np.concatenate([j, i, np.arange(n, dtype=np.int64)])
+    absrow = np.bincount(np.concatenate([i, j]), weights=np.abs(np.concatenate([v, v])).astype(np.float64),
+                         minlength=n)
+    diag = (1.0 + g_d.random(size=n) + absrow).astype(np.float32)
+    vals = np.concatenate([v, v, diag])
+    b = g_b.random(size=n, dtype=np.float32) * np.float32(2) - np.float32(1)
+    rp, ci, va = _csr(rows, cols, vals, n)
+    return rp, ci, va, b
