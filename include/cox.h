@@ -68,7 +68,9 @@ typedef enum {
   COX_OP_DOT = 1,
   COX_OP_SCAN = 2,
   COX_OP_COMPACT = 3,
-  COX_OP_SEGMENTED = 4
+  COX_OP_SEGMENTED = 4,
+  COX_OP_CG = 5,           /* n = rows; cfg: items_per_lane = rows per lane R */
+  COX_OP_GRID_EXCHANGE = 6 /* n = grid blocks */
 } cox_op;
 
 /* Schedule sigma of the chunked kernels.  A chunk is the tile of one
@@ -336,6 +338,78 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
 cox_status cox_plan_execute(cox_plan plan, void *stream);
 cox_status cox_plan_get_cfg(cox_plan plan, cox_cfg *cfg);
 cox_status cox_plan_destroy(cox_plan plan);
+
+/* ---------------------------------------------------------------------
+ * Grid-wide synchronisation (cooperative groups' this_grid().sync(),
+ * Sec. 2.2.2), which COX could not run (Sec. 5.1, Table 1: the
+ * conjugate-gradient sample).  The kernels below run on a cooperative
+ * launch, every block resident at once, and meet at a grid barrier: block
+ * arrivals are counted in eight groups (blocks b mod 8), the last arrival
+ * advances a generation word the other blocks wait for, and the writes of
+ * every block before the barrier are visible to every block after it.
+ * Waits are bounded: a barrier that does not complete within about a
+ * second ends the kernel early and sets the workspace's timeout flag
+ * (cox_workspace_status then reports COX_ERR_TIMEOUT; outputs are
+ * invalid).  The barrier words live in the workspace and are reset by
+ * every call.
+ * ------------------------------------------------------------------- */
+
+/* Largest grid (blocks of 1024 threads) a cooperative launch of the
+ * exchange kernel can hold on the current device. */
+cox_status cox_grid_capacity(int32_t *max_blocks);
+
+/* Exchange kernel (a check and a clock for the barrier): grid_blocks
+ * blocks of 1024 threads run `rounds` rounds; in round r thread t of block
+ * b writes fmix32(r << 20 ^ b << 10 ^ t) (MurmurHash3's 32-bit finaliser)
+ * to its slot, all blocks meet at a grid barrier, thread t adds (mod 2^32)
+ * the slot of thread t of block (b + r + 1) mod grid_blocks, and all
+ * blocks meet again.  out (device uint32[grid_blocks * 1024]) receives the
+ * sums.  1 <= grid_blocks <= cox_grid_capacity (COX_ERR_INVALID
+ * otherwise); ws: cox_workspace_bytes(COX_OP_GRID_EXCHANGE, COX_U32,
+ * grid_blocks, 0, NULL). */
+cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Conjugate gradient (Hestenes and Stiefel) for A x = b, A symmetric
+ * positive definite in CSR form, in ONE cooperative launch: the iteration
+ * loop runs inside the kernel with two grid barriers per iteration.
+ *   row_ptr : device int32[n + 1], row_ptr[0] = 0, nondecreasing,
+ *             row_ptr[n] = nnz;  col_idx : device int32[nnz] in [0, n);
+ *   val     : device float[nnz];  b : device float[n];
+ *   x       : device float[n], the start x_0 on entry, the result on exit;
+ *   result  : device int32[2] = {iterations k, reason}: 0 converged
+ *             (rr_k <= tol^2), 1 max_iter reached, 2 breakdown (<p, A p>
+ *             not positive), 3 a barrier wait gave up;
+ *   rr_hist : device double[max_iter + 1] (nullable): rr_0 .. rr_k.
+ * Arithmetic (binary32 vectors, binary64 scalars):
+ *   r = b - A x; rr_0 = <r, r>; iteration k (while rr_k > tol^2 and
+ *   k < max_iter): p = r (k = 0) or fmaf(beta, p, r) with
+ *   beta = (float)(rr_k / rr_{k-1}); q = A p; stop if not <p, q> > 0;
+ *   alpha = (float)(rr_k / <p, q>); x = fmaf(alpha, p, x);
+ *   r = fmaf(-alpha, q, r); rr_{k+1} = <r, r>.
+ *   (A v)_i: the row's entries in storage order, from +0.0f, with
+ *   acc = fmaf(a_ij, v_j, acc).
+ *   <u, v>: chunks of S = 32 * warps_per_block * items_per_lane rows; thread
+ *   (w, l) adds the exact products (double)u_i * (double)v_i of rows
+ *   cS + 32 W q + 32 w + l, q = 0 .. R-1, in FP64 from -0.0; the shfl_down
+ *   tree per warp, then over the W warp values (-0.0 beyond W); the chunk
+ *   values combined by the FP64 final tree of the reductions above.
+ * Results depend on (items_per_lane, warps_per_block) only, never on the
+ * grid.  cfg: items_per_lane 1, 2, 4 or 8, warps_per_block 8, 16 or 32
+ * (COX_ERR_UNSUPPORTED otherwise), grid_blocks 0 = one block per compute
+ * unit.  Malformed CSR (indices out of range) gives meaningless results
+ * but no access outside the arrays.  n < 2^31 - 2^13, nnz < 2^31.
+ * ws: cox_workspace_bytes(COX_OP_CG, COX_F32, n, 0, cfg). */
+cox_status cox_cg_solve(const int32_t *row_ptr, const int32_t *col_idx, const float *val, int64_t n, int64_t nnz,
+                        const float *b, float *x, int32_t max_iter, double tol, int32_t *result, double *rr_hist,
+                        const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
+/* The same solve as one launch per phase (2 per iteration, max_iter
+ * enqueued; the launches after a stop return at once): the baseline
+ * without grid barriers.  Identical results. */
+cox_status cox_cg_solve_per_phase(const int32_t *row_ptr, const int32_t *col_idx, const float *val, int64_t n,
+                                  int64_t nnz, const float *b, float *x, int32_t max_iter, double tol,
+                                  int32_t *result, double *rr_hist, const cox_cfg *cfg, void *ws, size_t ws_bytes,
+                                  void *stream);
 
 /* ---------------------------------------------------------------------
  * Bandwidth reference kernels (not part of the method): a plain read and

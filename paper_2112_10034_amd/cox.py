@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libcox.so")
 I32, U32, F32, BF16 = 0, 1, 2, 3
 PLAIN, TWOSUM = 0, 1
 SHFL_IDX, SHFL_UP, SHFL_DOWN, SHFL_XOR = 0, 1, 2, 3
-OP_REDUCE, OP_DOT, OP_SCAN, OP_COMPACT, OP_SEGMENTED = 0, 1, 2, 3, 4
+OP_REDUCE, OP_DOT, OP_SCAN, OP_COMPACT, OP_SEGMENTED, OP_CG, OP_GRID_EXCHANGE = 0, 1, 2, 3, 4, 5, 6
+CG_CONVERGED, CG_MAX_ITER, CG_BREAKDOWN, CG_ABORTED = 0, 1, 2, 3
 
 ERR_TIMEOUT = 7
 
@@ -73,6 +74,12 @@ _SIGS = {
     "cox_plan_execute": (_I, [_P, _P]),
     "cox_plan_get_cfg": (_I, [_P, C.POINTER(cox_cfg)]),
     "cox_plan_destroy": (_I, [_P]),
+    "cox_grid_capacity": (_I, [C.POINTER(C.c_int32)]),
+    "cox_grid_exchange": (_I, [C.c_int32, C.c_int32, _P, _P, _SZ, _P]),
+    "cox_cg_solve": (_I, [_P, _P, _P, _I64, _I64, _P, _P, C.c_int32, C.c_double, _P, _P, C.POINTER(cox_cfg), _P,
+                          _SZ, _P]),
+    "cox_cg_solve_per_phase": (_I, [_P, _P, _P, _I64, _I64, _P, _P, C.c_int32, C.c_double, _P, _P,
+                                    C.POINTER(cox_cfg), _P, _SZ, _P]),
     "cox_stream_read": (_I, [_P, _SZ, _P, C.c_int32, _P]),
     "cox_stream_copy": (_I, [_P, _P, _SZ, C.c_int32, _P]),
 }
@@ -340,6 +347,51 @@ def warp_dynamic(x, density, match_any=None, rank=None, rec=None, filtered=None,
     _check(lib().cox_warp_dynamic(_ptr(x), n, int(density), _ptr(match_any), _ptr(rank), _ptr(rec), _ptr(filtered),
                                   _ptr(count), _stream()), "cox_warp_dynamic")
     return match_any, rank, rec, filtered, count
+
+
+def grid_capacity():
+    """Largest grid of 1024-thread blocks a cooperative launch can hold."""
+    v = C.c_int32()
+    _check(lib().cox_grid_capacity(C.byref(v)), "cox_grid_capacity")
+    return v.value
+
+
+def grid_exchange(grid_blocks, rounds, out=None):
+    """Exchange kernel over a grid barrier; returns uint32 sums as an int32
+    device tensor [grid_blocks, 1024].  The workspace's timeout flag is
+    checked (synchronising)."""
+    out = torch.empty((grid_blocks, 1024), dtype=torch.int32, device="cuda") if out is None else out
+    ws = workspace(OP_GRID_EXCHANGE, U32, grid_blocks)
+    _check(lib().cox_grid_exchange(int(grid_blocks), int(rounds), _ptr(out), _ptr(ws.tensor), ws.nbytes, _stream()),
+           "cox_grid_exchange")
+    ws.status()
+    return out
+
+
+def cg_solve(row_ptr, col_idx, val, b, x, max_iter, tol=0.0, cfg=None, rr_hist=None, result=None,
+             per_phase=False):
+    """Conjugate gradient on the CSR system (row_ptr, col_idx, val) x = b,
+    updating the float32 device tensor x in place (it holds x_0 on entry).
+    One cooperative launch, or one launch per phase with per_phase=True.
+    Returns (result, rr_hist): result = int32 device tensor {iterations,
+    reason}, rr_hist = float64 device tensor [max_iter + 1]."""
+    _need(row_ptr, torch.int32, "row_ptr")
+    _need(col_idx, torch.int32, "col_idx")
+    _need(val, torch.float32, "val")
+    _need(b, torch.float32, "b")
+    _need(x, torch.float32, "x")
+    n, nnz = b.numel(), col_idx.numel()
+    if row_ptr.numel() != n + 1 or val.numel() != nnz or x.numel() != n:
+        raise CoxError(1, "cg_solve: inconsistent CSR / vector sizes")
+    dev = b.device
+    result = torch.zeros(2, dtype=torch.int32, device=dev) if result is None else result
+    rr_hist = torch.zeros(max_iter + 1, dtype=torch.float64, device=dev) if rr_hist is None else rr_hist
+    ws = workspace(OP_CG, F32, n, cfg=cfg)
+    fn = lib().cox_cg_solve_per_phase if per_phase else lib().cox_cg_solve
+    _check(fn(_ptr(row_ptr), _ptr(col_idx), _ptr(val), n, nnz, _ptr(b), _ptr(x), int(max_iter), float(tol),
+              _ptr(result), _ptr(rr_hist), _cfgp(cfg), _ptr(ws.tensor), ws.nbytes, _stream()),
+           "cox_cg_solve_per_phase" if per_phase else "cox_cg_solve")
+    return result, rr_hist
 
 
 def stream_read(x, sink=None, grid_blocks=0):

@@ -199,6 +199,14 @@ cox_status cox_default_cfg(cox_op op, cox_dtype dtype, cox_cfg *out) {
     out->items_per_lane = 32;
     out->warps_per_block = 8;
     break;
+  case COX_OP_CG:
+    out->items_per_lane = 4;
+    out->warps_per_block = 32;
+    break;
+  case COX_OP_GRID_EXCHANGE:
+    out->items_per_lane = 1;
+    out->warps_per_block = 32;
+    break;
   default: return COX_ERR_INVALID;
   }
   return COX_OK;
@@ -219,6 +227,8 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
     if (nseg < 0) return 0;
     return seg_workspace_bytes(nseg, n / S + nseg + 1);
   }
+  case COX_OP_CG: return cg_workspace_bytes(n, s.k, s.W);
+  case COX_OP_GRID_EXCHANGE: return gx_workspace_bytes(n);
   }
   return 0;
 }

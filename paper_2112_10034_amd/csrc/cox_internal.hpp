@@ -100,5 +100,9 @@ struct Sigma {
 cox_status resolve_cfg(cox_op op, cox_dtype dt, const cox_cfg *cfg, Sigma *out);
 // workspace bytes of a segmented call over nseg segments and at most maxch chunks
 size_t seg_workspace_bytes(int64_t nseg, int64_t maxch);
+// workspace bytes of a conjugate-gradient solve (n rows, schedule (R, W)) and
+// of the grid exchange over G blocks
+size_t cg_workspace_bytes(int64_t n, int R, int W);
+size_t gx_workspace_bytes(int64_t G);
 
 }  // namespace cox

@@ -1,0 +1,762 @@
+// Grid-wide barrier (cooperative groups' this_grid().sync(), Sec. 2.2.2) on
+// a cooperative launch, and two kernels built on it: an exchange kernel
+// that checks and times the barrier, and a conjugate-gradient solver whose
+// whole iteration loop runs in one launch -- the CG sample that Table 1
+// lists among the kernels COX could not run because of grid
+// synchronisation (Sec. 5.1).
+//
+// Memory protocol.  The per-XCD L2 caches of MI355X are not coherent with
+// each other for ordinary stores; an agent-scope release / acquire pair
+// makes them so by writing back and invalidating a whole L2, and with one
+// such pair per block a barrier costs 10 us at 256 blocks.  Here every
+// value that one block writes and another reads during a launch moves with
+// device-coherent (sc1) loads and stores instead -- the accesses of relaxed
+// agent-scope atomics, which bypass the non-coherent cached copies -- and
+// the barrier needs no cache maintenance: every wave waits for its own
+// stores to complete (s_waitcnt vmcnt(0)) before the block arrives, and
+// every read after the barrier is issued after the generation change was
+// seen.  Values a thread writes and later reads itself use ordinary
+// accesses.
+//
+// Barrier.  Blocks arrive in eight groups (block b in group b mod 8), so no
+// counter takes more than ceil(G / 8) of the atomics that serialise at one
+// address; the last arrival of a group counts the group at the top, and the
+// last group advances the generation the other blocks poll.  The waits are
+// bounded: one that runs out sets an abort word that every other wait also
+// obeys, so all blocks leave within one more timeout, and the call reports
+// COX_ERR_TIMEOUT through the workspace.
+//
+// CG (Hestenes and Stiefel; binary32 vectors, binary64 scalars, the
+// schedule of every inner product fixed by (R, W), see cox.h).  Two grid
+// barriers per iteration.  Phase 1 fuses p = r + beta p into the sparse
+// product: the block forms p over its rows and a halo of HALO rows on each
+// side in shared memory (from the previous p and r, with the same fmaf as
+// the stored p, so the same bits), stores its own rows' p (double-buffered
+// by iteration parity), and gathers from shared memory (columns outside the
+// window form p_j from global memory).  Phase 2 updates x and r with the
+// <r, r> partials.  Every block combines the chunk partials itself in the
+// fixed final order, so all blocks take the same decisions without a
+// broadcast.  Chunk c belongs to block c mod G in every phase, so results do
+// not depend on G.  When every block holds at most one chunk, x, r, p and q
+// of the block's rows stay in registers for the whole solve and only r and
+// p (for the other blocks' gathers) and the partials are stored.
+#include <algorithm>
+
+#include "cox_internal.hpp"
+
+namespace cox {
+
+// ---------------------------------------------------------------- barrier
+// Barrier words (uint32, one 128-byte line each), after the workspace
+// header: line g < 8 arrivals of group g, line 8 groups complete, line 9
+// generation, line 10 abort.
+enum : int { GB_LINE = 32, GB_GROUPS = 8, GB_TOP = 8 * 32, GB_GEN = 9 * 32, GB_ABORT = 10 * 32, GB_WORDS = 11 * 32 };
+constexpr size_t GB_BYTES = 2048;  // GB_WORDS * 4 rounded up
+constexpr uint32_t GRID_MAX_SPIN = 1u << 20;
+
+// device-coherent accesses
+__device__ __forceinline__ uint32_t ldc32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void stc32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float ldcf(const float *p) { return i2f((int)ldc32((const uint32_t *)p)); }
+__device__ __forceinline__ void stcf(float *p, float v) { stc32((uint32_t *)p, (uint32_t)f2i(v)); }
+__device__ __forceinline__ double ldcd(const double *p) {
+  return __builtin_bit_cast(double, __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void stcd(double *p, double v) {
+  __hip_atomic_store((uint64_t *)p, __builtin_bit_cast(uint64_t, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Every block of the (co-resident) grid calls this with every thread; the
+// device-coherent writes of all blocks before it are visible to the
+// device-coherent reads of all blocks after it.  false: the wait gave up,
+// and the kernel should finish without further barriers.
+__device__ bool grid_sync(uint32_t *bar, uint32_t *hdr) {
+  __shared__ uint32_t s_ok;
+  wait_stores();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t ok = 1u;
+    const uint32_t G = gridDim.x;
+    const uint32_t ng = G < GB_GROUPS ? G : GB_GROUPS;
+    const uint32_t g = blockIdx.x % ng;
+    const uint32_t members = (G - g + ng - 1) / ng;
+    // read before arriving: the generation cannot advance without us
+    const uint32_t gen = ldc32(&bar[GB_GEN]);
+    bool released = false;
+    if (__hip_atomic_fetch_add(&bar[g * GB_LINE], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == members - 1) {
+      // the resets land before the generation advances, so no arrival at
+      // the next barrier can precede them
+      stc32(&bar[g * GB_LINE], 0u);
+      wait_stores();
+      if (__hip_atomic_fetch_add(&bar[GB_TOP], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ng - 1) {
+        stc32(&bar[GB_TOP], 0u);
+        wait_stores();
+        stc32(&bar[GB_GEN], gen + 1u);
+        released = true;
+      }
+    }
+    if (!released) {
+      uint32_t spins = 0;
+      while (ldc32(&bar[GB_GEN]) == gen) {
+        if (ldc32(&bar[GB_ABORT]) != 0u || ++spins > GRID_MAX_SPIN) {
+          stc32(&bar[GB_ABORT], 1u);
+          stc32(&hdr[HDR_ERR], 1u);
+          ok = 0u;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0u;
+}
+
+__global__ void k_grid_clear(uint32_t *bar, int words) {
+  for (int i = threadIdx.x; i < words; i += blockDim.x) bar[i] = 0u;
+}
+
+// ---------------------------------------------------------------- exchange
+// MurmurHash3's 32-bit finaliser (Appleby), the payload of the exchange
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+
+constexpr int GX_BLOCK = 1024;
+
+// round r: write own row, barrier, add the row of block (b + r + 1) mod G,
+// barrier
+__global__ __launch_bounds__(GX_BLOCK) void k_grid_exchange(uint32_t *slot, uint32_t *out, int rounds, uint32_t *bar,
+                                                            uint32_t *hdr) {
+  const uint32_t G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
+  uint32_t sum = 0u;
+  for (int r = 0; r < rounds; r++) {
+    stc32(&slot[(size_t)b * GX_BLOCK + t], fmix32(((uint32_t)r << 20) ^ (b << 10) ^ t));
+    if (!grid_sync(bar, hdr)) break;
+    const uint32_t src = (uint32_t)(((uint64_t)b + (uint64_t)r + 1u) % G);
+    sum += ldc32(&slot[(size_t)src * GX_BLOCK + t]);
+    if (!grid_sync(bar, hdr)) break;
+  }
+  out[(size_t)b * GX_BLOCK + t] = sum;
+}
+
+// ---------------------------------------------------------------- CG
+constexpr int HALO = 64;  // rows of the shared-memory window beyond the chunk on each side
+
+struct CgState {
+  uint32_t stop;
+  uint32_t pad;
+  double rr[2];  // rr_k at slot k & 1 (per-phase launches)
+};
+
+struct CgArgs {
+  const int32_t *rp, *ci;
+  const float *val, *b;
+  float *x, *r, *p[2], *q;
+  double *prr, *ppq;  // chunk partials of <r, r> and <p, A p>
+  int64_t nch;
+  int32_t n, nnz;
+  int32_t max_iter;
+  double tol2;
+  int32_t *result;
+  double *rr_hist;
+  uint32_t *bar, *hdr;
+  CgState *state;
+};
+
+// shared memory of one block
+template <int R, int W>
+struct CgShared {
+  double slot[32];
+  double fin[256];
+  double bcast;
+  float win[32 * W * R + 2 * HALO];
+};
+
+// xor butterfly over a logical warp: every lane ends with the value lane 0
+// of the shfl_down tree (offsets 16 .. 1) holds
+__device__ __forceinline__ double tree64(double v) {
+  v = v + xor_lane_d<16>(v);
+  v = v + xor_lane_d<8>(v);
+  v = v + xor_lane_d<4>(v);
+  v = v + xor_lane_d<2>(v);
+  v = v + xor_lane_d<1>(v);
+  return v;
+}
+
+// chunk value of a per-thread FP64 sum: warp trees, then warp 0's tree over
+// the W warp values (-0.0 beyond W); thread 0 stores it.  Ends with a block
+// barrier, so the shared window may be reused after it.
+template <int W, class SH>
+__device__ __forceinline__ void chunk_store(double s, double *part, int64_t c, SH &sh) {
+  const int t = threadIdx.x, l = t & 31;
+  s = tree64(s);
+  if (l == 0) sh.slot[t >> 5] = s;
+  __syncthreads();
+  if (t < 32) {
+    const double v = tree64(l < W ? sh.slot[l] : -0.0);
+    if (t == 0) stcd(&part[c], v);
+  }
+  __syncthreads();
+}
+
+// final combine of nch chunk values, computed by every block: thread j <
+// 256 sums values j, j + 256, ... from -0.0 (a batch padded with -0.0 adds
+// nothing); each group of 32 runs the tree; the tree again over the 8
+// group values (-0.0 beyond 8)
+template <class SH>
+__device__ __forceinline__ double final64(const double *part, int64_t nch, SH &sh) {
+  constexpr int FB = 8;
+  const int t = threadIdx.x, l = t & 31;
+  if (t < 256) {
+    double s = -0.0;
+    for (int64_t c0 = t; c0 < nch; c0 += 256 * FB) {
+      double v[FB];
+#pragma unroll
+      for (int u = 0; u < FB; u++) v[u] = c0 + 256 * u < nch ? ldcd(&part[c0 + 256 * u]) : -0.0;
+#pragma unroll
+      for (int u = 0; u < FB; u++) s = s + v[u];
+    }
+    sh.fin[t] = s;
+  }
+  __syncthreads();
+  if (t < 32) {
+    double top = -0.0;
+#pragma unroll
+    for (int vw = 0; vw < 8; vw++) {
+      const double v = tree64(sh.fin[32 * vw + l]);
+      if (l == vw) top = v;
+    }
+    top = tree64(top);
+    if (t == 0) sh.bcast = top;
+  }
+  __syncthreads();
+  return sh.bcast;
+}
+
+// row bounds, clamped so that malformed CSR cannot read outside the arrays
+__device__ __forceinline__ void row_bounds(const CgArgs &a, int32_t i, int32_t &lo, int32_t &hi) {
+  int32_t u = a.rp[i], v = a.rp[i + 1];
+  u = u < 0 ? 0 : (u > a.nnz ? a.nnz : u);
+  v = v < u ? u : (v > a.nnz ? a.nnz : v);
+  lo = u;
+  hi = v;
+}
+__device__ __forceinline__ uint32_t col_at(const CgArgs &a, int32_t jj) {
+  const uint32_t j = (uint32_t)a.ci[jj];
+  return j < (uint32_t)a.n ? j : (uint32_t)a.n - 1u;
+}
+
+// (A v)_i for the R rows of a thread, the rows' entries stepped together
+// so that the R rows' loads are in flight at once; each row accumulates in
+// storage order from +0.0f with fmaf.  vj(j) gives v_j.
+template <int R, class V>
+__device__ __forceinline__ void spmv_rows(const CgArgs &a, const int32_t (&row)[R], float (&acc)[R], V vj) {
+  int32_t lo[R], hi[R];
+  int32_t len = 0;
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    acc[q] = 0.0f;
+    if (row[q] < a.n) {
+      row_bounds(a, row[q], lo[q], hi[q]);
+    } else {
+      lo[q] = 0;
+      hi[q] = 0;
+    }
+    len = max(len, hi[q] - lo[q]);
+  }
+  for (int32_t s = 0; s < len; s++) {
+    uint32_t j[R];
+    float v[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const bool ok = lo[q] + s < hi[q];
+      j[q] = ok ? col_at(a, lo[q] + s) : 0u;
+      v[q] = ok ? a.val[lo[q] + s] : 0.0f;
+    }
+    float g[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) g[q] = lo[q] + s < hi[q] ? vj(j[q]) : 0.0f;
+#pragma unroll
+    for (int q = 0; q < R; q++)
+      if (lo[q] + s < hi[q]) acc[q] = __builtin_fmaf(v[q], g[q], acc[q]);
+  }
+}
+
+template <int R, int W>
+__device__ __forceinline__ void rows_of(int64_t c, int32_t (&row)[R]) {
+  constexpr int BT = 32 * W;
+#pragma unroll
+  for (int q = 0; q < R; q++) row[q] = (int32_t)(c * (BT * R) + BT * q + threadIdx.x);
+}
+
+// p = r (first) or fmaf(beta, p_prev, r) over chunk c's rows and the halo,
+// into sh.win (w0 = first row of the window); ends with a block barrier
+template <int R, int W, class SH>
+__device__ __forceinline__ int32_t cg_window(const CgArgs &a, int64_t c, bool first, float beta, const float *pp,
+                                             SH &sh, int32_t &wn) {
+  constexpr int BT = 32 * W, S = BT * R;
+  static_assert(2 * HALO <= BT, "window loop covers S + 2 HALO rows in R + 1 steps");
+  const int64_t lo = c * S;
+  const int32_t w0 = (int32_t)(lo > HALO ? lo - HALO : 0);
+  const int32_t w1 = (int32_t)(lo + S + HALO < a.n ? lo + S + HALO : a.n);
+  float rv[R + 1], pv[R + 1];
+#pragma unroll
+  for (int m = 0; m <= R; m++) {
+    const int32_t j = w0 + BT * m + (int32_t)threadIdx.x;
+    const bool ok = j < w1;
+    rv[m] = ok ? ldcf(a.r + j) : 0.0f;
+    pv[m] = ok && !first ? ldcf(pp + j) : 0.0f;
+  }
+#pragma unroll
+  for (int m = 0; m <= R; m++) {
+    const int32_t j = w0 + BT * m + (int32_t)threadIdx.x;
+    if (j < w1) sh.win[j - w0] = first ? rv[m] : __builtin_fmaf(beta, pv[m], rv[m]);
+  }
+  __syncthreads();
+  wn = w1 - w0;
+  return w0;
+}
+
+// r = b - A x, partials of <r, r>; the resident form keeps x and r
+template <int R, int W, class SH>
+__device__ __forceinline__ void cg_phase0_chunk(const CgArgs &a, int64_t c, SH &sh, float (&xv)[R], float (&rv)[R]) {
+  int32_t row[R];
+  float ax[R];
+  rows_of<R, W>(c, row);
+  spmv_rows<R>(a, row, ax, [&](uint32_t j) { return a.x[j]; });
+  double s = -0.0;
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    xv[q] = 0.0f;
+    rv[q] = 0.0f;
+    if (row[q] < a.n) {
+      xv[q] = a.x[row[q]];
+      rv[q] = a.b[row[q]] - ax[q];
+      stcf(a.r + row[q], rv[q]);
+      s = s + (double)rv[q] * (double)rv[q];
+    }
+  }
+  chunk_store<W>(s, a.prr, c, sh);
+}
+
+// p (into p[k & 1]) and q = A p, partials of <p, q>
+template <int R, int W, class SH>
+__device__ __forceinline__ void cg_phase1_chunk(const CgArgs &a, int64_t c, int k, float beta, SH &sh, float (&pv)[R],
+                                                float (&qv)[R]) {
+  const bool first = k == 0;
+  const float *pp = a.p[(k + 1) & 1];
+  float *pn = a.p[k & 1];
+  int32_t wn;
+  const int32_t w0 = cg_window<R, W>(a, c, first, beta, pp, sh, wn);
+  int32_t row[R];
+  rows_of<R, W>(c, row);
+  spmv_rows<R>(a, row, qv, [&](uint32_t j) {
+    const uint32_t o = j - (uint32_t)w0;
+    if (o < (uint32_t)wn) return sh.win[o];
+    const float rj = ldcf(a.r + j);
+    return first ? rj : __builtin_fmaf(beta, ldcf(pp + j), rj);
+  });
+  double s = -0.0;
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    pv[q] = 0.0f;
+    if (row[q] < a.n) {
+      pv[q] = sh.win[row[q] - w0];
+      stcf(pn + row[q], pv[q]);
+      s = s + (double)pv[q] * (double)qv[q];
+    }
+  }
+  chunk_store<W>(s, a.ppq, c, sh);
+}
+
+// x = fmaf(alpha, p, x), r = fmaf(-alpha, q, r), partials of <r, r>
+template <int R, int W, class SH>
+__device__ __forceinline__ void cg_phase2_chunk(const CgArgs &a, int64_t c, float alpha, SH &sh, const float (&pv)[R],
+                                                const float (&qv)[R], float (&xv)[R], float (&rv)[R]) {
+  int32_t row[R];
+  rows_of<R, W>(c, row);
+  double s = -0.0;
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    if (row[q] < a.n) {
+      xv[q] = __builtin_fmaf(alpha, pv[q], xv[q]);
+      rv[q] = __builtin_fmaf(-alpha, qv[q], rv[q]);
+      stcf(a.r + row[q], rv[q]);
+      s = s + (double)rv[q] * (double)rv[q];
+    }
+  }
+  chunk_store<W>(s, a.prr, c, sh);
+}
+
+// streaming forms: per-row values through memory (x and q are only ever
+// read back by the thread that wrote them)
+template <int R, int W, class SH>
+__device__ void cg_phase0(const CgArgs &a, SH &sh) {
+  for (int64_t c = blockIdx.x; c < a.nch; c += gridDim.x) {
+    float xv[R], rv[R];
+    cg_phase0_chunk<R, W>(a, c, sh, xv, rv);
+  }
+}
+
+template <int R, int W, class SH>
+__device__ void cg_phase1(const CgArgs &a, int k, float beta, SH &sh) {
+  for (int64_t c = blockIdx.x; c < a.nch; c += gridDim.x) {
+    float pv[R], qv[R];
+    cg_phase1_chunk<R, W>(a, c, k, beta, sh, pv, qv);
+    int32_t row[R];
+    rows_of<R, W>(c, row);
+#pragma unroll
+    for (int q = 0; q < R; q++)
+      if (row[q] < a.n) a.q[row[q]] = qv[q];
+  }
+}
+
+template <int R, int W, class SH>
+__device__ void cg_phase2(const CgArgs &a, int k, float alpha, SH &sh) {
+  const float *pn = a.p[k & 1];
+  for (int64_t c = blockIdx.x; c < a.nch; c += gridDim.x) {
+    int32_t row[R];
+    rows_of<R, W>(c, row);
+    float pv[R], qv[R], xv[R], rv[R];
+#pragma unroll
+    for (int q = 0; q < R; q++) {
+      const bool ok = row[q] < a.n;
+      const int32_t i = ok ? row[q] : 0;
+      pv[q] = ok ? ldcf(pn + i) : 0.0f;
+      rv[q] = ok ? ldcf(a.r + i) : 0.0f;
+      qv[q] = ok ? a.q[i] : 0.0f;
+      xv[q] = ok ? a.x[i] : 0.0f;
+    }
+    cg_phase2_chunk<R, W>(a, c, alpha, sh, pv, qv, xv, rv);
+#pragma unroll
+    for (int q = 0; q < R; q++)
+      if (row[q] < a.n) a.x[row[q]] = xv[q];
+  }
+}
+
+enum : int32_t { CG_CONVERGED = 0, CG_MAX_ITER = 1, CG_BREAKDOWN = 2, CG_ABORTED = 3 };
+
+__device__ __forceinline__ bool lead() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// the whole solve in one cooperative launch, per-row values through memory
+template <int R, int W>
+__global__ __launch_bounds__(32 * W) void k_cg(CgArgs a) {
+  __shared__ CgShared<R, W> sh;
+  int32_t k = 0, reason = CG_ABORTED;
+  cg_phase0<R, W>(a, sh);
+  if (grid_sync(a.bar, a.hdr)) {
+    double rr = final64(a.prr, a.nch, sh), rr_prev = 0.0;
+    for (;; k++) {
+      if (lead() && a.rr_hist) a.rr_hist[k] = rr;
+      if (rr <= a.tol2) {
+        reason = CG_CONVERGED;
+        break;
+      }
+      if (k == a.max_iter) {
+        reason = CG_MAX_ITER;
+        break;
+      }
+      cg_phase1<R, W>(a, k, k ? (float)(rr / rr_prev) : 0.0f, sh);
+      if (!grid_sync(a.bar, a.hdr)) break;
+      const double pq = final64(a.ppq, a.nch, sh);
+      if (!(pq > 0.0)) {
+        reason = CG_BREAKDOWN;
+        break;
+      }
+      cg_phase2<R, W>(a, k, (float)(rr / pq), sh);
+      if (!grid_sync(a.bar, a.hdr)) break;
+      rr_prev = rr;
+      rr = final64(a.prr, a.nch, sh);
+    }
+  }
+  if (lead()) {
+    a.result[0] = k;
+    a.result[1] = reason;
+  }
+}
+
+// the same solve with at most one chunk per block (gridDim.x >= nch): the
+// block's x, r, p and q stay in registers; x is stored once at the end
+template <int R, int W>
+__global__ __launch_bounds__(32 * W) void k_cg_res(CgArgs a) {
+  __shared__ CgShared<R, W> sh;
+  const int64_t c = blockIdx.x;
+  const bool own = c < a.nch;  // uniform over the block
+  float xv[R], rv[R], pv[R], qv[R];
+  int32_t k = 0, reason = CG_ABORTED;
+  if (own) cg_phase0_chunk<R, W>(a, c, sh, xv, rv);
+  if (grid_sync(a.bar, a.hdr)) {
+    double rr = final64(a.prr, a.nch, sh), rr_prev = 0.0;
+    for (;; k++) {
+      if (lead() && a.rr_hist) a.rr_hist[k] = rr;
+      if (rr <= a.tol2) {
+        reason = CG_CONVERGED;
+        break;
+      }
+      if (k == a.max_iter) {
+        reason = CG_MAX_ITER;
+        break;
+      }
+      if (own) cg_phase1_chunk<R, W>(a, c, k, k ? (float)(rr / rr_prev) : 0.0f, sh, pv, qv);
+      if (!grid_sync(a.bar, a.hdr)) break;
+      const double pq = final64(a.ppq, a.nch, sh);
+      if (!(pq > 0.0)) {
+        reason = CG_BREAKDOWN;
+        break;
+      }
+      if (own) cg_phase2_chunk<R, W>(a, c, (float)(rr / pq), sh, pv, qv, xv, rv);
+      if (!grid_sync(a.bar, a.hdr)) break;
+      rr_prev = rr;
+      rr = final64(a.prr, a.nch, sh);
+    }
+  }
+  if (own) {
+    int32_t row[R];
+    rows_of<R, W>(c, row);
+#pragma unroll
+    for (int q = 0; q < R; q++)
+      if (row[q] < a.n) a.x[row[q]] = xv[q];
+  }
+  if (lead()) {
+    a.result[0] = k;
+    a.result[1] = reason;
+  }
+}
+
+// the same phases as one launch each (the baseline without grid barriers);
+// a stopped solve turns the remaining launches into no-ops
+template <int R, int W>
+__global__ __launch_bounds__(32 * W) void k_cg_p0(CgArgs a) {
+  __shared__ CgShared<R, W> sh;
+  cg_phase0<R, W>(a, sh);
+}
+
+template <int R, int W>
+__global__ __launch_bounds__(32 * W) void k_cg_p1(CgArgs a, int32_t k) {
+  __shared__ CgShared<R, W> sh;
+  if (a.state->stop) return;
+  const double rr = final64(a.prr, a.nch, sh);
+  if (lead() && a.rr_hist) a.rr_hist[k] = rr;
+  const int32_t reason = rr <= a.tol2 ? CG_CONVERGED : (k == a.max_iter ? CG_MAX_ITER : -1);
+  if (reason >= 0) {
+    if (lead()) {
+      a.result[0] = k;
+      a.result[1] = reason;
+      a.state->stop = 1u;
+    }
+    return;
+  }
+  if (lead()) a.state->rr[k & 1] = rr;
+  cg_phase1<R, W>(a, k, k ? (float)(rr / a.state->rr[(k + 1) & 1]) : 0.0f, sh);
+}
+
+template <int R, int W>
+__global__ __launch_bounds__(32 * W) void k_cg_p2(CgArgs a, int32_t k) {
+  __shared__ CgShared<R, W> sh;
+  if (a.state->stop) return;
+  const double pq = final64(a.ppq, a.nch, sh);
+  if (!(pq > 0.0)) {
+    if (lead()) {
+      a.result[0] = k;
+      a.result[1] = CG_BREAKDOWN;
+      a.state->stop = 1u;
+    }
+    return;
+  }
+  cg_phase2<R, W>(a, k, (float)(a.state->rr[k & 1] / pq), sh);
+}
+
+// ---------------------------------------------------------------- host side
+struct CgLayout {
+  size_t bar, state, r, p0, p1, q, prr, ppq, total;
+};
+
+static size_t up256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static CgLayout cg_layout(int64_t n, int R, int W) {
+  const int64_t S = (int64_t)32 * W * R;
+  const int64_t nch = (n + S - 1) / S;
+  const size_t vec = up256((size_t)n * 4);
+  CgLayout L;
+  L.bar = WS_HEADER;
+  L.state = L.bar + GB_BYTES;
+  L.r = L.state + 256;
+  L.p0 = L.r + vec;
+  L.p1 = L.p0 + vec;
+  L.q = L.p1 + vec;
+  L.prr = L.q + vec;
+  L.ppq = L.prr + up256((size_t)nch * 8);
+  L.total = L.ppq + up256((size_t)nch * 8);
+  return L;
+}
+
+size_t cg_workspace_bytes(int64_t n, int R, int W) { return cg_layout(n, R, W).total; }
+size_t gx_workspace_bytes(int64_t G) { return WS_HEADER + GB_BYTES + (size_t)G * GX_BLOCK * 4; }
+
+template <int R, int W>
+struct CgKernels {
+  static const void *coop() { return (const void *)k_cg<R, W>; }
+  static const void *coop_res() { return (const void *)k_cg_res<R, W>; }
+  static void per_phase(const CgArgs &a, int G, hipStream_t st) {
+    hipLaunchKernelGGL((k_cg_p0<R, W>), dim3(G), dim3(32 * W), 0, st, a);
+    for (int32_t k = 0; k <= a.max_iter; k++) {
+      hipLaunchKernelGGL((k_cg_p1<R, W>), dim3(G), dim3(32 * W), 0, st, a, k);
+      if (k < a.max_iter) hipLaunchKernelGGL((k_cg_p2<R, W>), dim3(G), dim3(32 * W), 0, st, a, k);
+    }
+  }
+};
+
+struct CgPick {
+  const void *coop, *coop_res;
+  void (*per_phase)(const CgArgs &, int, hipStream_t);
+};
+
+template <int W>
+static bool pick_r(int R, CgPick *p) {
+  switch (R) {
+  case 1: *p = {CgKernels<1, W>::coop(), CgKernels<1, W>::coop_res(), CgKernels<1, W>::per_phase}; return true;
+  case 2: *p = {CgKernels<2, W>::coop(), CgKernels<2, W>::coop_res(), CgKernels<2, W>::per_phase}; return true;
+  case 4: *p = {CgKernels<4, W>::coop(), CgKernels<4, W>::coop_res(), CgKernels<4, W>::per_phase}; return true;
+  case 8: *p = {CgKernels<8, W>::coop(), CgKernels<8, W>::coop_res(), CgKernels<8, W>::per_phase}; return true;
+  }
+  return false;
+}
+
+static bool cg_pick(int R, int W, CgPick *p) {
+  switch (W) {
+  case 8: return pick_r<8>(R, p);
+  case 16: return pick_r<16>(R, p);
+  case 32: return pick_r<32>(R, p);
+  }
+  return false;
+}
+
+static cox_status cg_run(const int32_t *row_ptr, const int32_t *col_idx, const float *val, int64_t n, int64_t nnz,
+                         const float *b, float *x, int32_t max_iter, double tol, int32_t *result, double *rr_hist,
+                         const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream, bool coop) {
+  if (n < 0 || n > INT32_MAX - 8192 || nnz < 0 || nnz > INT32_MAX || max_iter < 0 || max_iter == INT32_MAX)
+    return COX_ERR_INVALID;
+  if (!result || (n > 0 && (!row_ptr || !val || !b || !x || (nnz > 0 && !col_idx)))) return COX_ERR_INVALID;
+  Sigma sg;
+  cox_status st = resolve_cfg(COX_OP_CG, COX_F32, cfg, &sg);
+  if (st != COX_OK) return st;
+  CgPick pk;
+  if (!cg_pick(sg.k, sg.W, &pk)) return COX_ERR_UNSUPPORTED;
+  const CgLayout L = cg_layout(n, sg.k, sg.W);
+  if (!ws || ws_bytes < L.total) return COX_ERR_WORKSPACE;
+  const int64_t S = (int64_t)32 * sg.W * sg.k;
+  const int64_t nch = (n + S - 1) / S;
+  const int block = 32 * sg.W;
+  const int cap = std::min(blocks_per_cu(pk.coop, block), blocks_per_cu(pk.coop_res, block)) * device_cus();
+  int G = sg.G;
+  if (G == 0) G = device_cus();
+  if (G > cap) {
+    if (sg.G) return COX_ERR_INVALID;
+    G = cap;
+  }
+  if (G > nch) G = (int)(nch > 0 ? nch : 1);
+  if (G < 1) return COX_ERR_INVALID;
+  char *w = (char *)ws;
+  CgArgs a;
+  a.rp = row_ptr;
+  a.ci = col_idx;
+  a.val = val;
+  a.b = b;
+  a.x = x;
+  a.r = (float *)(w + L.r);
+  a.p[0] = (float *)(w + L.p0);
+  a.p[1] = (float *)(w + L.p1);
+  a.q = (float *)(w + L.q);
+  a.prr = (double *)(w + L.prr);
+  a.ppq = (double *)(w + L.ppq);
+  a.nch = nch;
+  a.n = (int32_t)n;
+  a.nnz = (int32_t)nnz;
+  a.max_iter = max_iter;
+  a.tol2 = tol * tol;
+  a.result = result;
+  a.rr_hist = rr_hist;
+  a.bar = (uint32_t *)(w + L.bar);
+  a.hdr = (uint32_t *)w;
+  a.state = (CgState *)(w + L.state);
+  hipStream_t hs = (hipStream_t)stream;
+  // barrier words and solver state start at zero on every call
+  hipLaunchKernelGGL(k_grid_clear, dim3(1), dim3(256), 0, hs, a.bar, (int)((GB_BYTES + 256) / 4));
+  if ((st = launch_status()) != COX_OK) return st;
+  if (coop) {
+    // one chunk per block at most: the register-resident kernel
+    void *args[] = {&a};
+    const hipError_t e = hipLaunchCooperativeKernel(G >= nch ? pk.coop_res : pk.coop, dim3(G), dim3(block), args, 0, hs);
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      return COX_ERR_HIP;
+    }
+    return COX_OK;
+  }
+  pk.per_phase(a, G, hs);
+  return launch_status();
+}
+
+}  // namespace cox
+
+using namespace cox;
+
+extern "C" {
+
+cox_status cox_cg_solve(const int32_t *row_ptr, const int32_t *col_idx, const float *val, int64_t n, int64_t nnz,
+                        const float *b, float *x, int32_t max_iter, double tol, int32_t *result, double *rr_hist,
+                        const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream) {
+  return cg_run(row_ptr, col_idx, val, n, nnz, b, x, max_iter, tol, result, rr_hist, cfg, ws, ws_bytes, stream,
+                true);
+}
+
+cox_status cox_cg_solve_per_phase(const int32_t *row_ptr, const int32_t *col_idx, const float *val, int64_t n,
+                                  int64_t nnz, const float *b, float *x, int32_t max_iter, double tol,
+                                  int32_t *result, double *rr_hist, const cox_cfg *cfg, void *ws, size_t ws_bytes,
+                                  void *stream) {
+  return cg_run(row_ptr, col_idx, val, n, nnz, b, x, max_iter, tol, result, rr_hist, cfg, ws, ws_bytes, stream,
+                false);
+}
+
+cox_status cox_grid_capacity(int32_t *max_blocks) {
+  if (!max_blocks) return COX_ERR_INVALID;
+  *max_blocks = blocks_per_cu((const void *)k_grid_exchange, GX_BLOCK) * device_cus();
+  return launch_status();
+}
+
+cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out, void *ws, size_t ws_bytes,
+                             void *stream) {
+  if (grid_blocks < 1 || rounds < 0 || !out) return COX_ERR_INVALID;
+  if (grid_blocks > blocks_per_cu((const void *)k_grid_exchange, GX_BLOCK) * device_cus()) return COX_ERR_INVALID;
+  if (!ws || ws_bytes < gx_workspace_bytes(grid_blocks)) return COX_ERR_WORKSPACE;
+  char *w = (char *)ws;
+  uint32_t *bar = (uint32_t *)(w + WS_HEADER);
+  uint32_t *slot = (uint32_t *)(w + WS_HEADER + GB_BYTES);
+  uint32_t *hdr = (uint32_t *)w;
+  hipStream_t hs = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_grid_clear, dim3(1), dim3(256), 0, hs, bar, (int)(GB_BYTES / 4));
+  cox_status st = launch_status();
+  if (st != COX_OK) return st;
+  void *args[] = {&slot, &out, &rounds, &bar, &hdr};
+  const hipError_t e = hipLaunchCooperativeKernel((const void *)k_grid_exchange, dim3(grid_blocks), dim3(GX_BLOCK),
+                                                  args, 0, hs);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return COX_ERR_HIP;
+  }
+  return COX_OK;
+}
+
+}  // extern "C"
