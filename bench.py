@@ -166,6 +166,59 @@ def other_kernels(fg, reps=10):
     return res
 
 
+def grid_sync_bench(iters=50, reps=3, rounds=2000):
+    """Grid-wide barriers.  The exchange kernel (two barriers per round) at
+    one and two 1024-thread blocks per compute unit gives the barrier
+    latency.  The conjugate-gradient solve of the tridiagonal system at
+    2^20 and 2^24 rows (iters iterations, tol = 0) runs once as one
+    cooperative launch and once as one launch per phase; every timed solve
+    starts from x = 0 (the zero fill is inside the timed region).
+    Algorithmic bytes per iteration: row_ptr 4 (n + 1) and the entries
+    8 nnz, plus per row 16 bytes when the block's rows stay in registers
+    (p and r gathered, p and r stored) or 40 bytes when they stream
+    through memory (also q stored, and p, q, x, r read, x stored)."""
+    import torch
+
+    from paper_2112_10034_amd import cox, inputs
+
+    res = {}
+    cap = cox.grid_capacity()
+    for G in sorted({cap // 2, cap}):
+        out = torch.empty((G, 1024), dtype=torch.int32, device="cuda")
+        ms = _timed(lambda: cox.grid_exchange(G, rounds, out), reps)
+        res[f"barrier_us_g{G}"] = round(ms * 1e3 / (2 * rounds), 3)
+    R, W, _ = cox.default_cfg(cox.OP_CG, cox.F32)
+    for n in inputs.CG_N:
+        rp, ci, val, b = inputs.cg_tridiag(n)
+        d = [torch.from_numpy(a).cuda() for a in (rp, ci, val, b)]
+        x = torch.zeros(n, dtype=torch.float32, device="cuda")
+        nnz = ci.size
+        nch = -(-n // (32 * W * R))
+        resident = nch <= torch.cuda.get_device_properties(0).multi_processor_count
+        row_bytes = 16 if resident else 40
+        entry = {"rows": n, "nnz": int(nnz), "iterations": iters, "sigma": [R, W],
+                 "registers_resident": bool(resident)}
+        for name, pp, rb in (("one_launch", False, row_bytes), ("per_phase", True, 40)):
+            def solve():
+                x.zero_()
+                return cox.cg_solve(*d, x, iters, 0.0, per_phase=pp)
+            ms = _timed(solve, reps)
+            k = int(solve()[0][0].item())
+            assert k == iters, (name, k)
+            nbytes = 4 * (n + 1) + 8 * nnz + rb * n
+            us = ms * 1e3 / iters
+            gbs = nbytes / (us * 1e-6) / 1e9
+            entry[name] = {"us_per_iteration": round(us, 3), "algorithmic_bytes_per_iteration": int(nbytes),
+                           "gb_s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        entry["speedup_one_launch"] = round(entry["per_phase"]["us_per_iteration"] /
+                                            entry["one_launch"]["us_per_iteration"], 3)
+        res[f"cg_tridiag_2p{n.bit_length() - 1}"] = entry
+        del d, x
+    for ws in cox._ws_cache.values():
+        ws.status()
+    return res
+
+
 def batching(reps=5, base_reps=2, per_segment=True):
     """The segmented workload (10,000 lognormal segments): the fused
     reduce + scan + compaction as one autotuned graph-captured launch vs the
@@ -234,6 +287,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batching", action="store_true", help="skip the segmented batching comparison")
     ap.add_argument("--no-others", action="store_true", help="skip the kernels outside the timed step")
+    ap.add_argument("--no-grid", action="store_true", help="skip the grid-barrier and conjugate-gradient timings")
     ap.add_argument("--no-per-segment", action="store_true",
                     help="skip the one-launch-per-segment baseline of the batching comparison")
     args = ap.parse_args()
@@ -391,6 +445,9 @@ def main():
         del xg, fg
         torch.cuda.empty_cache()
         out["batching"] = batching(per_segment=not args.no_per_segment)
+    if not args.no_grid:
+        log("grid barrier and conjugate gradient")
+        out["grid_sync"] = grid_sync_bench()
     if not args.no_cpu_baseline:
         sample = min(args.cpu_sample, n)
         log(f"cpu baseline: oracle on {sample} elements")

@@ -25,7 +25,7 @@ so tests can draw smaller instances from the same recipe):
    - tridiagonal: off-diagonal pairs a(i, i+1) = a(i+1, i) = -U[0, 1),
      diagonal 3 + U[0, 1) (strictly diagonally dominant, hence positive
      definite, eigenvalues in (1, 6)); right-hand side U[-1, 1); n = 2^20
-     rows (the size of the CUDA sample's system) and 2^24;
+     rows and 2^24;
    - irregular: about n * deg / 2 off-diagonal pairs (i, j), i != j, with i
      drawn as floor(n * U^2) (so low rows are long) and j uniform, value
      -U[0, 1) mirrored to (j, i) (duplicate pairs stay as separate
