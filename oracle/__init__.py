@@ -73,6 +73,7 @@ def lib():
             "coxo_code5": (I, [P, P, P, P, I]),
             "coxo_uniform_branch": (I, [P, P, I64, P]),
             "coxo_grid_exchange": (I, [I, I, I, P]),
+            "coxo_tile_sort_kv_u32": (I, [P, P, P, P, I64]),
             "coxo_cg": (I, [P, P, P, I64, P, P, I, C.c_double, I, I, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -217,6 +218,16 @@ def tile_sort_u32(keys, group=32):
     out = np.empty_like(keys)
     _check(lib().coxo_tile_sort_u32(_p(keys), _p(out), keys.size, group), "tile_sort_u32")
     return out
+
+
+def tile_sort_kv_u32(keys, vals):
+    """Stable sort of every 32-pair group by unsigned key; returns
+    (out_keys, out_vals)."""
+    k = _c(keys, np.uint32)
+    v = _c(vals, np.uint32)
+    ok, ov = np.empty_like(k), np.empty_like(v)
+    _check(lib().coxo_tile_sort_kv_u32(_p(k), _p(v), _p(ok), _p(ov), k.size), "tile_sort_kv_u32")
+    return ok, ov
 
 
 def tile_reduce_i32(x, tile):

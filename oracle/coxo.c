@@ -1195,6 +1195,46 @@ int coxo_tile_sort_u32(const uint32_t *keys, uint32_t *out, int64_t n, int G) {
   return run_blocks((n + 31) / 32, sort_block, &c);
 }
 
+/* key-value tile sort: every group of 32 consecutive (key, value) pairs
+ * (a partial last group: its valid pairs) in ascending unsigned key order,
+ * pairs with equal keys in their original order (a stable sort: sorting by
+ * (key, position in the group), which makes the result unique).  The plain
+ * definition, by insertion sort. */
+typedef struct {
+  const uint32_t *keys, *vals;
+  uint32_t *ok, *ov;
+  int64_t n;
+} kv_ctx;
+
+static void kv_block(void *p, int64_t g) {
+  kv_ctx *c = (kv_ctx *)p;
+  const int64_t e0 = 32 * g;
+  const int m = (int)(c->n - e0 < 32 ? c->n - e0 : 32);
+  uint32_t k[32], v[32];
+  for (int i = 0; i < m; i++) {
+    uint32_t kk = c->keys[e0 + i], vv = c->vals[e0 + i];
+    int j = i;
+    while (j > 0 && k[j - 1] > kk) {
+      k[j] = k[j - 1];
+      v[j] = v[j - 1];
+      j--;
+    }
+    k[j] = kk;
+    v[j] = vv;
+  }
+  for (int i = 0; i < m; i++) {
+    c->ok[e0 + i] = k[i];
+    c->ov[e0 + i] = v[i];
+  }
+}
+
+int coxo_tile_sort_kv_u32(const uint32_t *keys, const uint32_t *vals, uint32_t *out_keys, uint32_t *out_vals,
+                          int64_t n) {
+  if (n < 0) return COXO_ERR_INVALID;
+  kv_ctx c = {keys, vals, out_keys, out_vals, n};
+  return run_blocks((n + 31) / 32, kv_block, &c);
+}
+
 /* ================================================================== */
 /* tile<T> reduce: out[g] = wrap32 sum of x[gT .. gT+T-1] (zero pads)   */
 /*   via tile.shfl_down(v, o) with o = T/2 .. 1 (width T); the tile's   */

@@ -182,6 +182,37 @@ def test_tile_sort_adversarial(oracle_mod):
         assert np.array_equal(o.tile_sort_u32(c), np.sort(c))
 
 
+@pytest.mark.parametrize("n,kmax", [(32, 4), (32 * 1000, 8), (32 * 1000 + 17, 1 << 32), (31, 2), (1, 5)])
+def test_tile_sort_kv_is_the_stable_sort(oracle_mod, n, kmax):
+    g = np.random.default_rng(n)
+    keys = g.integers(0, kmax, n, dtype=np.uint64).astype(np.uint32)
+    vals = g.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    ok, ov = oracle_mod.tile_sort_kv_u32(keys, vals)
+    for s in range(0, n, 32):
+        order = np.argsort(keys[s:s + 32], kind="stable")
+        assert np.array_equal(ok[s:s + 32], keys[s:s + 32][order])
+        assert np.array_equal(ov[s:s + 32], vals[s:s + 32][order])
+    # the keys agree with the bitonic key-only sort (a different algorithm)
+    assert np.array_equal(ok, oracle_mod.tile_sort_u32(keys))
+
+
+def test_tile_sort_kv_stability_and_edges(oracle_mod):
+    o = oracle_mod
+    idx = np.arange(64, dtype=np.uint32)
+    # all keys equal: the identity permutation
+    ok, ov = o.tile_sort_kv_u32(np.full(64, 9, np.uint32), idx)
+    assert np.array_equal(ov, idx)
+    # reversed keys with values = positions: values reverse within each group
+    keys = np.tile(np.arange(32, dtype=np.uint32)[::-1], 2)
+    ok, ov = o.tile_sort_kv_u32(keys, idx)
+    assert np.array_equal(ov, np.concatenate([idx[:32][::-1], idx[32:][::-1]]))
+    # maximal keys in a partial group keep their order; ties at 0 and 2^32-1
+    keys = np.array([0xFFFFFFFF, 0, 0xFFFFFFFF, 0, 5], np.uint32)
+    ok, ov = o.tile_sort_kv_u32(keys, np.arange(5, dtype=np.uint32))
+    assert ok.tolist() == [0, 0, 5, 0xFFFFFFFF, 0xFFFFFFFF] and ov.tolist() == [1, 3, 4, 0, 2]
+    assert o.tile_sort_kv_u32(np.zeros(0, np.uint32), np.zeros(0, np.uint32))[0].size == 0
+
+
 # ---------------------------------------------------------------- K-TR
 @pytest.mark.parametrize("T", inputs.TILE_SIZES)
 def test_tile_reduce_plain_definition(oracle_mod, T):
