@@ -114,6 +114,7 @@ def other_kernels(fg, reps=10):
     """The kernels outside the timed step, each timed on its own: the
     block reduce (2^20 int32), the masked warp operations at three
     densities, the dynamic groups and the tile reductions (2^26 int32),
+    the key-value tile sort (2^28 pairs),
     and the precision
     variants over 2^28 elements (float32 and bfloat16, sum and dot, plain
     and TwoSum).  Their timing does not depend on the values, so the
@@ -149,6 +150,15 @@ def other_kernels(fg, reps=10):
                                                _timed(lambda: cox.tile_reduce(xm, T, to), reps))
     del xm, out, rec
     n = fg.numel()
+    # key-value tile sort over 2^28 pairs (a network's time does not depend
+    # on the values): uint32 keys, 4-byte values; 16 bytes per pair
+    gk = torch.Generator(device="cuda")
+    gk.manual_seed(2112100344)
+    kk = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, device="cuda", generator=gk)
+    kv = torch.arange(n, dtype=torch.int32, device="cuda")
+    ok_, ov_ = torch.empty_like(kk), torch.empty_like(kv)
+    res["tile_sort_kv_2p28"] = _entry(n, 16 * n, _timed(lambda: cox.tile_sort_kv(kk, kv, None, ok_, ov_), reps))
+    del kk, kv, ok_, ov_
     g2 = torch.Generator(device="cuda")
     g2.manual_seed(2112100343)
     f2 = torch.randn(n, dtype=torch.float32, device="cuda", generator=g2)

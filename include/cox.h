@@ -219,6 +219,19 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
 cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
                          const cox_cfg *cfg, void *stream);
 
+/* Key-value form (a workload built from the same shuffle network): every
+ * group of 32 consecutive pairs (keys[i], vals[i]) ordered by unsigned key,
+ * pairs with equal keys in their original order (a stable sort, so the
+ * result is unique).  The network sorts (key, position in the group);
+ * each output then takes the value at its position.  A partial last group
+ * is sorted among its valid pairs.  keys, out_keys: uint32[n], 16-byte
+ * aligned (may be the same buffer); vals: uint32[n] payloads of any 4-byte
+ * type; out_vals: uint32[n], 16-byte aligned, not overlapping vals
+ * (COX_ERR_INVALID if it is vals).  cfg->items_per_lane: pairs per lane,
+ * 1, 2, 4 or 8 (0 = 4). */
+cox_status cox_tile_sort_kv(const uint32_t *keys, const uint32_t *vals, uint32_t *out_keys, uint32_t *out_vals,
+                            int64_t n, int tile, const cox_cfg *cfg, void *stream);
+
 /* thread_block_tile<T> reduction (static cooperative groups, section
  * 2.2.2; warp-function support, section 3.2): out[g] = wrap32 sum of
  * x[gT .. gT+T-1], the value tile.shfl_down(v, o), o = T/2 .. 1, leaves in

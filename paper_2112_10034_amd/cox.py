@@ -59,6 +59,7 @@ _SIGS = {
     "cox_warp_scan": (_I, [_P, _P, _I64, C.POINTER(cox_cfg), _P, _SZ, _P]),
     "cox_ballot_compact": (_I, [_P, _I64, _P, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
     "cox_tile_sort": (_I, [_P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
+    "cox_tile_sort_kv": (_I, [_P, _P, _P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
     "cox_tile_reduce": (_I, [_P, _I64, _I, _P, _P]),
     "cox_warp_masked": (_I, [_P, _I64, _I, _P, _P, _P]),
     "cox_warp_dynamic": (_I, [_P, _I64, _I, _P, _P, _P, _P, _P, _P]),
@@ -311,6 +312,24 @@ def tile_sort(keys, tile=32, cfg=None, out=None):
     _check(lib().cox_tile_sort(_ptr(keys), _ptr(out), keys.numel(), int(tile), _cfgp(cfg), _stream()),
            "cox_tile_sort")
     return out
+
+
+def tile_sort_kv(keys, vals, cfg=None, out_keys=None, out_vals=None):
+    """Stable sort of every 32-pair group by unsigned key (keys: int32 view
+    of uint32 keys; vals: any 4-byte int32 / float32 tensor).  Returns
+    (out_keys, out_vals)."""
+    _need(keys, torch.int32, "keys")
+    if vals.dtype not in (torch.int32, torch.float32):
+        raise TypeError("vals must be a 4-byte tensor (int32 or float32)")
+    _need(vals, vals.dtype, "vals")
+    n = keys.numel()
+    if vals.numel() != n:
+        raise ValueError("keys and vals differ in size")
+    out_keys = torch.empty_like(keys) if out_keys is None else out_keys
+    out_vals = torch.empty_like(vals) if out_vals is None else out_vals
+    _check(lib().cox_tile_sort_kv(_ptr(keys), _ptr(vals), _ptr(out_keys), _ptr(out_vals), n, 32, _cfgp(cfg),
+                                  _stream()), "cox_tile_sort_kv")
+    return out_keys, out_vals
 
 
 def tile_reduce(x, tile, out=None):

@@ -138,6 +138,118 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *keys, uint32_
   }
 }
 
+// Key-value form: the network runs on 64-bit composites (key << 32 |
+// position in the group), so equal keys keep their original order (a
+// stable sort, which makes the result unique) and every comparison is one
+// 64-bit compare.  After the network each output takes its value from the
+// group's original values at its position (the group's 128 bytes, loaded
+// once).
+template <int K, int PM, int LB>
+__device__ __forceinline__ void cx_layer_kv(uint64_t (&c)[K], int g) {
+  constexpr int RM = PM & (K - 1);
+  constexpr int LM = PM / K;
+  if constexpr (LM == 0) {
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+      const int r2 = r ^ RM;
+      if (r < r2) {
+        const uint64_t a = c[r], b = c[r2];
+        c[r] = a < b ? a : b;
+        c[r2] = a < b ? b : a;
+      }
+    }
+  } else {
+    uint64_t other[K];
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+      const uint64_t v = c[r ^ RM];
+      const uint32_t lo = (uint32_t)xor_lane<LM>((int)(uint32_t)v);
+      const uint32_t hi = (uint32_t)xor_lane<LM>((int)(uint32_t)(v >> 32));
+      other[r] = ((uint64_t)hi << 32) | lo;
+    }
+    const bool upper = (g & (LB / K)) != 0;
+#pragma unroll
+    for (int r = 0; r < K; r++) {
+      const bool less = other[r] < c[r];
+      c[r] = (less != upper) ? other[r] : c[r];
+    }
+  }
+}
+
+template <int K, int K2, int J>
+__device__ __forceinline__ void half_cleaners_kv(uint64_t (&c)[K], int g) {
+  if constexpr (J >= 1) {
+    cx_layer_kv<K, J, J>(c, g);
+    half_cleaners_kv<K, K2, J / 2>(c, g);
+  }
+}
+
+template <int K, int K2>
+__device__ __forceinline__ void merge_stages_kv(uint64_t (&c)[K], int g) {
+  if constexpr (K2 <= 32) {
+    cx_layer_kv<K, K2 - 1, K2 / 2>(c, g);
+    half_cleaners_kv<K, K2, K2 / 4>(c, g);
+    merge_stages_kv<K, K2 * 2>(c, g);
+  }
+}
+
+// same rounds and row layout as k_tile_sort; keys / out_keys may be the
+// same buffer, vals / out_vals may not
+template <int K>
+__global__ __launch_bounds__(256) void k_tile_sort_kv(const uint32_t *keys, const uint32_t *__restrict__ vals,
+                                                      uint32_t *out_keys, uint32_t *__restrict__ out_vals,
+                                                      int64_t n) {
+  constexpr int LG = 32 / K;
+  constexpr int U = K >= 8 ? 1 : 8 / K > 4 ? 4 : 8 / K;
+  const int g = (int)(threadIdx.x % LG);
+  const int64_t nvec = (n + K - 1) / K;
+  const int64_t per_round = (int64_t)gridDim.x * 256 * U;
+  const int64_t rounds = (nvec + per_round - 1) / per_round;
+  for (int64_t it = 0; it < rounds; it++) {
+    const int64_t vbase = it * per_round + (int64_t)blockIdx.x * 256 * U + threadIdx.x;
+    const bool full = (vbase - threadIdx.x + 256 * U) * K <= n;
+    uint64_t c[U][K];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t e0 = (vbase + 256 * u) * K;
+      uint32_t key[K];
+      if (full) {
+        load_keys<K>(keys + e0, key);
+      } else {
+#pragma unroll
+        for (int r = 0; r < K; r++) key[r] = e0 + r < n ? keys[e0 + r] : 0xffffffffu;
+      }
+#pragma unroll
+      for (int r = 0; r < K; r++) c[u][r] = ((uint64_t)key[r] << 32) | (uint32_t)(g * K + r);
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) merge_stages_kv<K, 2>(c[u], g);
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int64_t e0 = (vbase + 256 * u) * K;
+      const int64_t gb = e0 & ~(int64_t)31;
+      uint32_t key[K], val[K];
+#pragma unroll
+      for (int r = 0; r < K; r++) {
+        key[r] = (uint32_t)(c[u][r] >> 32);
+        const bool ok = full || e0 + r < n;
+        val[r] = ok ? vals[gb + ((uint32_t)c[u][r] & 31u)] : 0u;
+      }
+      if (full) {
+        store_keys<K>(out_keys + e0, key);
+        store_keys<K>(out_vals + e0, val);
+      } else {
+#pragma unroll
+        for (int r = 0; r < K; r++)
+          if (e0 + r < n) {
+            out_keys[e0 + r] = key[r];
+            out_vals[e0 + r] = val[r];
+          }
+      }
+    }
+  }
+}
+
 using sort_fn = void (*)(const uint32_t *, uint32_t *, int64_t);
 static sort_fn pick_sort(int k) {
   switch (k) {
@@ -146,6 +258,17 @@ static sort_fn pick_sort(int k) {
   case 4: return k_tile_sort<4>;
   case 8: return k_tile_sort<8>;
   case 16: return k_tile_sort<16>;
+  }
+  return nullptr;
+}
+
+using sort_kv_fn = void (*)(const uint32_t *, const uint32_t *, uint32_t *, uint32_t *, int64_t);
+static sort_kv_fn pick_sort_kv(int k) {
+  switch (k) {
+  case 1: return k_tile_sort_kv<1>;
+  case 2: return k_tile_sort_kv<2>;
+  case 4: return k_tile_sort_kv<4>;
+  case 8: return k_tile_sort_kv<8>;
   }
   return nullptr;
 }
@@ -170,5 +293,24 @@ extern "C" cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t
   const int grid = persistent_grid((const void *)fn, 256, (nvec + 256 * U - 1) / (256 * U),
                                    cfg ? cfg->grid_blocks : 0, 0, 2);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, out, n);
+  return launch_status();
+}
+
+extern "C" cox_status cox_tile_sort_kv(const uint32_t *keys, const uint32_t *vals, uint32_t *out_keys,
+                                       uint32_t *out_vals, int64_t n, int tile, const cox_cfg *cfg, void *stream) {
+  if (n < 0 || tile != 32) return COX_ERR_INVALID;
+  const int k = (cfg && cfg->items_per_lane) ? cfg->items_per_lane : 4;
+  if (cfg && cfg->grid_blocks < 0) return COX_ERR_INVALID;
+  sort_kv_fn fn = pick_sort_kv(k);
+  if (!fn) return k > 0 && k <= 32 && (k & (k - 1)) == 0 ? COX_ERR_UNSUPPORTED : COX_ERR_INVALID;
+  if (n == 0) return COX_OK;
+  if (!keys || !vals || !out_keys || !out_vals) return COX_ERR_INVALID;
+  if (!aligned16(keys) || !aligned16(out_keys) || !aligned16(out_vals)) return COX_ERR_ALIGN;
+  if (out_vals == vals) return COX_ERR_INVALID;
+  const int64_t nvec = (n + k - 1) / k;
+  const int U = k >= 8 ? 1 : 8 / k > 4 ? 4 : 8 / k;
+  const int grid = persistent_grid((const void *)fn, 256, (nvec + 256 * U - 1) / (256 * U),
+                                   cfg ? cfg->grid_blocks : 0, 0, 2);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, vals, out_keys, out_vals, n);
   return launch_status();
 }
