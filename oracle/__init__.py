@@ -74,6 +74,7 @@ def lib():
             "coxo_uniform_branch": (I, [P, P, I64, P]),
             "coxo_grid_exchange": (I, [I, I, I, P]),
             "coxo_tile_sort_kv_u32": (I, [P, P, P, P, I64]),
+            "coxo_integral_image_u8": (I, [P, I64, I64, P]),
             "coxo_cg": (I, [P, P, P, I64, P, P, I, C.c_double, I, I, P, P]),
         }
         for name, (res, args) in sig.items():
@@ -284,6 +285,15 @@ def grid_exchange(G, rounds, block=1024):
     out = np.zeros(G * block, np.uint32)
     _check(lib().coxo_grid_exchange(G, block, rounds, _p(out)), "grid_exchange")
     return out.reshape(G, block)
+
+
+def integral_image_u8(img):
+    """Summed-area table of a uint8 image [H, W] as uint32 (mod 2^32)."""
+    im = _c(img, np.uint8)
+    H, W = im.shape
+    sat = np.empty((H, W), np.uint32)
+    _check(lib().coxo_integral_image_u8(_p(im), H, W, _p(sat)), "integral_image_u8")
+    return sat
 
 
 CG_CONVERGED, CG_MAX_ITER, CG_BREAKDOWN = 0, 1, 2

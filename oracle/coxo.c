@@ -1778,6 +1778,45 @@ int coxo_uniform_branch(const int32_t *cond, const int32_t *x, int64_t n, int32_
 }
 
 /* ================================================================== */
+/* integral image (summed-area table), the application of the shuffle    */
+/* scans in Table 1 (shfl_intimage_rows, shfl_vertical_shfl):            */
+/*   sat[y][x] = sum of img[y'][x'] over y' <= y, x' <= x  (mod 2^32)    */
+/* The plain definition: an inclusive prefix along every row, then one   */
+/* down every column, in uint32 arithmetic (exact modulo 2^32, so the    */
+/* order of the additions does not matter).                              */
+/* ================================================================== */
+typedef struct {
+  const uint8_t *img;
+  uint32_t *sat;
+  int64_t H, W;
+} ii_ctx;
+
+static void ii_rows(void *p, int64_t y) {
+  ii_ctx *c = (ii_ctx *)p;
+  uint32_t s = 0;
+  for (int64_t x = 0; x < c->W; x++) {
+    s += c->img[y * c->W + x];
+    c->sat[y * c->W + x] = s;
+  }
+}
+static void ii_cols(void *p, int64_t x) {
+  ii_ctx *c = (ii_ctx *)p;
+  uint32_t s = 0;
+  for (int64_t y = 0; y < c->H; y++) {
+    s += c->sat[y * c->W + x];
+    c->sat[y * c->W + x] = s;
+  }
+}
+
+int coxo_integral_image_u8(const uint8_t *img, int64_t H, int64_t W, uint32_t *sat) {
+  if (H < 0 || W < 0) return COXO_ERR_INVALID;
+  ii_ctx c = {img, sat, H, W};
+  int st = run_blocks(H, ii_rows, &c);
+  if (st == COXO_OK) st = run_blocks(W, ii_cols, &c);
+  return st;
+}
+
+/* ================================================================== */
 /* grid-wide barriers (this_grid().sync(), Sec. 2.2.2; COX could not run */
 /* kernels that need one, Sec. 5.1 and Table 1)                         */
 /*                                                                      */

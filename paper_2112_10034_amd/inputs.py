@@ -31,6 +31,8 @@ so tests can draw smaller instances from the same recipe):
      -U[0, 1) mirrored to (j, i) (duplicate pairs stay as separate
      entries); diagonal 1 + U[0, 1) + the row's sum of |off-diagonal|;
      right-hand side U[-1, 1).
+6. integral image: uint8 pixels uniform in [0, 255], row-major [H, W];
+   8192 x 8192 for the benchmark, ragged shapes for the tests.
 """
 import numpy as np
 
@@ -38,6 +40,7 @@ BASE_SEED = 2112100340
 
 FULL_N = {0: 1 << 20, 1: 1 << 28, 2: 1 << 26, 3: 1 << 28}
 CG_N = (1 << 20, 1 << 24)
+IMAGE_HW = (8192, 8192)
 NSEG = 10_000
 SEG_MEDIAN = 2000
 SEG_SIGMA = 1.97
@@ -289,3 +292,9 @@ def cg_irregular(n, deg=6, seed=None):
     b = g_b.random(size=n, dtype=np.float32) * np.float32(2) - np.float32(1)
     rp, ci, va = _csr(rows, cols, vals, n)
     return rp, ci, va, b
+
+
+def image_u8(H=IMAGE_HW[0], W=IMAGE_HW[1], seed=None):
+    """uint8 image [H, W] of workload 6."""
+    (g,) = _streams(6, 1, seed)
+    return g.integers(0, 256, size=(H, W), dtype=np.uint8)
