@@ -114,7 +114,7 @@ def other_kernels(fg, reps=10):
     """The kernels outside the timed step, each timed on its own: the
     block reduce (2^20 int32), the masked warp operations at three
     densities, the dynamic groups and the tile reductions (2^26 int32),
-    the key-value tile sort (2^28 pairs),
+    the key-value tile sort (2^28 pairs), the integral image (8192 x 8192),
     and the precision
     variants over 2^28 elements (float32 and bfloat16, sum and dot, plain
     and TwoSum).  Their timing does not depend on the values, so the
@@ -159,6 +159,13 @@ def other_kernels(fg, reps=10):
     ok_, ov_ = torch.empty_like(kk), torch.empty_like(kv)
     res["tile_sort_kv_2p28"] = _entry(n, 16 * n, _timed(lambda: cox.tile_sort_kv(kk, kv, None, ok_, ov_), reps))
     del kk, kv, ok_, ov_
+    # integral image of the 8192 x 8192 uint8 image: 1 byte read and 4
+    # written per pixel
+    img = torch.from_numpy(inputs.image_u8()).cuda()
+    H, W = img.shape
+    sat = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    res[f"integral_image_{H}x{W}"] = _entry(H * W, 5 * H * W, _timed(lambda: cox.integral_image(img, sat), reps))
+    del img, sat
     g2 = torch.Generator(device="cuda")
     g2.manual_seed(2112100343)
     f2 = torch.randn(n, dtype=torch.float32, device="cuda", generator=g2)

@@ -70,7 +70,8 @@ typedef enum {
   COX_OP_COMPACT = 3,
   COX_OP_SEGMENTED = 4,
   COX_OP_CG = 5,           /* n = rows; cfg: items_per_lane = rows per lane R */
-  COX_OP_GRID_EXCHANGE = 6 /* n = grid blocks */
+  COX_OP_GRID_EXCHANGE = 6, /* n = grid blocks */
+  COX_OP_INTEGRAL_IMAGE = 7 /* n = image height, nseg = image width */
 } cox_op;
 
 /* Schedule sigma of the chunked kernels.  A chunk is the tile of one
@@ -351,6 +352,23 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
 cox_status cox_plan_execute(cox_plan plan, void *stream);
 cox_status cox_plan_get_cfg(cox_plan plan, cox_cfg *cfg);
 cox_status cox_plan_destroy(cox_plan plan);
+
+/* Integral image (summed-area table), the application of the warp
+ * shuffle scans that Table 1 lists (the row pass and the vertical pass of
+ * the CUDA scan sample):
+ *     sat[y][x] = sum of img[y'][x'] over y' <= y and x' <= x   (mod 2^32)
+ * img: device uint8[height][width], row-major; sat: device
+ * uint32[height][width].  Tiles of 64 rows x 1024 columns are reduced
+ * (column sums, row sums, tile totals), the column sums are scanned down
+ * the bands, and every tile is then scanned row by row (a 32-lane shuffle
+ * scan per row) with its carries from above and from the left: three
+ * launches, about 6.1 bytes per pixel.  The result is exact (uint32
+ * arithmetic).  A width that is a multiple of 4 with img 4-byte and sat
+ * 16-byte aligned uses 4-pixel loads and 16-byte stores; any other shape
+ * works element by element.  ws: cox_workspace_bytes(COX_OP_INTEGRAL_IMAGE,
+ * COX_U32, height, width, NULL). */
+cox_status cox_integral_image(const uint8_t *img, int64_t height, int64_t width, uint32_t *sat, void *ws,
+                              size_t ws_bytes, void *stream);
 
 /* ---------------------------------------------------------------------
  * Grid-wide synchronisation (cooperative groups' this_grid().sync(),

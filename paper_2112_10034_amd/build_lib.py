@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libcox.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["capi.hip", "reduce.hip", "scan.hip", "sort.hip", "tile.hip", "stream.hip", "segmented.hip", "dynamic.hip", "grid.hip"]
+SOURCES = ["capi.hip", "reduce.hip", "scan.hip", "sort.hip", "tile.hip", "stream.hip", "segmented.hip", "dynamic.hip", "grid.hip", "image.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

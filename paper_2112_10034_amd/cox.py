@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libcox.so")
 I32, U32, F32, BF16 = 0, 1, 2, 3
 PLAIN, TWOSUM = 0, 1
 SHFL_IDX, SHFL_UP, SHFL_DOWN, SHFL_XOR = 0, 1, 2, 3
-OP_REDUCE, OP_DOT, OP_SCAN, OP_COMPACT, OP_SEGMENTED, OP_CG, OP_GRID_EXCHANGE = 0, 1, 2, 3, 4, 5, 6
+OP_REDUCE, OP_DOT, OP_SCAN, OP_COMPACT, OP_SEGMENTED, OP_CG, OP_GRID_EXCHANGE, OP_INTEGRAL_IMAGE = range(8)
 CG_CONVERGED, CG_MAX_ITER, CG_BREAKDOWN, CG_ABORTED = 0, 1, 2, 3
 
 ERR_TIMEOUT = 7
@@ -75,6 +75,7 @@ _SIGS = {
     "cox_plan_execute": (_I, [_P, _P]),
     "cox_plan_get_cfg": (_I, [_P, C.POINTER(cox_cfg)]),
     "cox_plan_destroy": (_I, [_P]),
+    "cox_integral_image": (_I, [_P, _I64, _I64, _P, _P, _SZ, _P]),
     "cox_grid_capacity": (_I, [C.POINTER(C.c_int32)]),
     "cox_grid_exchange": (_I, [C.c_int32, C.c_int32, _P, _P, _SZ, _P]),
     "cox_cg_solve": (_I, [_P, _P, _P, _I64, _I64, _P, _P, C.c_int32, C.c_double, _P, _P, C.POINTER(cox_cfg), _P,
@@ -366,6 +367,20 @@ def warp_dynamic(x, density, match_any=None, rank=None, rec=None, filtered=None,
     _check(lib().cox_warp_dynamic(_ptr(x), n, int(density), _ptr(match_any), _ptr(rank), _ptr(rec), _ptr(filtered),
                                   _ptr(count), _stream()), "cox_warp_dynamic")
     return match_any, rank, rec, filtered, count
+
+
+def integral_image(img, out=None):
+    """Summed-area table (mod 2^32) of a uint8 device image [H, W]; returns
+    an int32 tensor holding the uint32 sums."""
+    _need(img, torch.uint8, "img")
+    if img.dim() != 2:
+        raise ValueError("img must be 2-D [height, width]")
+    H, W = img.shape
+    out = torch.empty((H, W), dtype=torch.int32, device=img.device) if out is None else out
+    ws = workspace(OP_INTEGRAL_IMAGE, U32, H, W)
+    _check(lib().cox_integral_image(_ptr(img), H, W, _ptr(out), _ptr(ws.tensor), ws.nbytes, _stream()),
+           "cox_integral_image")
+    return out
 
 
 def grid_capacity():

@@ -207,6 +207,10 @@ cox_status cox_default_cfg(cox_op op, cox_dtype dtype, cox_cfg *out) {
     out->items_per_lane = 1;
     out->warps_per_block = 32;
     break;
+  case COX_OP_INTEGRAL_IMAGE:
+    out->items_per_lane = 4;
+    out->warps_per_block = 8;
+    break;
   default: return COX_ERR_INVALID;
   }
   return COX_OK;
@@ -229,6 +233,7 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
   }
   case COX_OP_CG: return cg_workspace_bytes(n, s.k, s.W);
   case COX_OP_GRID_EXCHANGE: return gx_workspace_bytes(n);
+  case COX_OP_INTEGRAL_IMAGE: return nseg < 0 ? 0 : ii_workspace_bytes(n, nseg);
   }
   return 0;
 }

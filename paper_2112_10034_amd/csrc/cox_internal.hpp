@@ -104,5 +104,7 @@ size_t seg_workspace_bytes(int64_t nseg, int64_t maxch);
 // of the grid exchange over G blocks
 size_t cg_workspace_bytes(int64_t n, int R, int W);
 size_t gx_workspace_bytes(int64_t G);
+// workspace bytes of an integral image of height x width pixels
+size_t ii_workspace_bytes(int64_t H, int64_t W);
 
 }  // namespace cox
