@@ -55,24 +55,51 @@ struct IiArgs {
   uint32_t *colsum;   // [nb][W]: column sums, then their exclusive prefix T
   uint32_t *rowsum;   // [ns][H]
   uint32_t *total;    // [nb][ns]
-  bool vec;           // W % 4 == 0 and the buffers aligned: 4-pixel loads, 16-byte stores
 };
 
-// the 4 pixels of a thread in row y (columns x .. x + 3; zero past W)
-__device__ __forceinline__ void ii_pixels(const IiArgs &a, int64_t y, int64_t x, uint32_t (&p)[4]) {
+// The 4 pixels of a thread in row y (columns x .. x + 3; zero past W, and
+// zero for rows past the tile).  VEC (W % 4 == 0, image 4-byte aligned):
+// one 4-byte load.
+template <bool VEC>
+__device__ __forceinline__ void ii_pixels(const IiArgs &a, int64_t y, bool row_ok, int64_t x, uint32_t (&p)[4]) {
   const uint8_t *row = a.img + y * a.W;
-  if (a.vec) {
-    uint32_t w = 0u;
-    if (x < a.W) w = ld_stream1(row + x);
+  if constexpr (VEC) {
+    const uint32_t w = row_ok && x < a.W ? ld_stream1(row + x) : 0u;
 #pragma unroll
     for (int j = 0; j < 4; j++) p[j] = (w >> (8 * j)) & 0xffu;
   } else {
 #pragma unroll
-    for (int j = 0; j < 4; j++) p[j] = x + j < a.W ? (uint32_t)row[x + j] : 0u;
+    for (int j = 0; j < 4; j++) p[j] = row_ok && x + j < a.W ? (uint32_t)row[x + j] : 0u;
   }
 }
 
+// Sums of 8 values over a logical warp, one value per row: a butterfly
+// that halves the values a lane holds at every step (xor 16, 8, 4), then
+// two plain steps (xor 2, 1).  Returns, in every lane, the warp sum of
+// value ((lane >> 2) & 7).
+__device__ __forceinline__ uint32_t ii_warp_sum8(const uint32_t (&v)[8]) {
+  const int l = llane();
+  uint32_t a[4], b[2];
+  const bool h16 = (l & 16) != 0, h8 = (l & 8) != 0, h4 = (l & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 4; i++) {
+    const uint32_t send = h16 ? v[i] : v[i + 4];
+    a[i] = (h16 ? v[i + 4] : v[i]) + (uint32_t)xor_lane<16>((int)send);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; i++) {
+    const uint32_t send = h8 ? a[i] : a[i + 2];
+    b[i] = (h8 ? a[i + 2] : a[i]) + (uint32_t)xor_lane<8>((int)send);
+  }
+  uint32_t c = (h4 ? b[1] : b[0]) + (uint32_t)xor_lane<4>((int)(h4 ? b[0] : b[1]));
+  c += (uint32_t)xor_lane<2>((int)c);
+  c += (uint32_t)xor_lane<1>((int)c);
+  return c;
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(II_BT) void k_ii_reduce(IiArgs a) {
+  static_assert(II_RB == 8, "row sums are reduced 8 rows at a time");
   __shared__ uint32_t s_rows[II_BT / 32][II_TH];
   __shared__ uint32_t s_tot[2];
   const int t = threadIdx.x, w = t >> 5, l = t & 31;
@@ -84,19 +111,19 @@ __global__ __launch_bounds__(II_BT) void k_ii_reduce(IiArgs a) {
     for (int r0 = 0; r0 < rows; r0 += II_RB) {
       uint32_t p[II_RB][4];
 #pragma unroll
-      for (int r = 0; r < II_RB; r++) {
-        if (r0 + r < rows) ii_pixels(a, y0 + r0 + r, x, p[r]);
-        else p[r][0] = p[r][1] = p[r][2] = p[r][3] = 0u;
-      }
+      for (int r = 0; r < II_RB; r++) ii_pixels<VEC>(a, y0 + r0 + r, r0 + r < rows, x, p[r]);
+      uint32_t rp[II_RB];
 #pragma unroll
       for (int r = 0; r < II_RB; r++) {
         cs[0] += p[r][0];
         cs[1] += p[r][1];
         cs[2] += p[r][2];
         cs[3] += p[r][3];
-        const uint32_t rs = ii_warp_sum(p[r][0] + p[r][1] + p[r][2] + p[r][3]);
-        if (l == 0 && r0 + r < rows) s_rows[w][r0 + r] = rs;
+        rp[r] = p[r][0] + p[r][1] + p[r][2] + p[r][3];
       }
+      const uint32_t rs = ii_warp_sum8(rp);
+      const int r = (l >> 2) & 7;
+      if ((l & 3) == 0 && r0 + r < rows) s_rows[w][r0 + r] = rs;
     }
 #pragma unroll
     for (int j = 0; j < 4; j++)
@@ -117,9 +144,9 @@ __global__ __launch_bounds__(II_BT) void k_ii_reduce(IiArgs a) {
   }
 }
 
-// exclusive prefix of every column's band sums, 16 bands per batch of loads
+// exclusive prefix of every column's band sums, 64 bands per batch of loads
 __global__ __launch_bounds__(256) void k_ii_colscan(IiArgs a) {
-  constexpr int NB = 16;
+  constexpr int NB = 64;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.W; x += (int64_t)gridDim.x * blockDim.x) {
     uint32_t run = 0u;
     for (int64_t b0 = 0; b0 < a.nb; b0 += NB) {
@@ -135,6 +162,7 @@ __global__ __launch_bounds__(256) void k_ii_colscan(IiArgs a) {
   }
 }
 
+template <bool VEC>
 __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
   __shared__ uint32_t s_lin[II_TH];             // row carries, prefixed inside each 32-row half
   __shared__ uint32_t s_left[II_TH];            // corner + row carries, prefixed over the tile's rows
@@ -170,15 +198,17 @@ __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
       s_left[t] = corner + s_lin[t] + (t >= 32 ? s_lin[31] : 0u);
     }
     __syncthreads();
+    // rounds of II_RB rows; the next round's pixels are requested before
+    // the current round's barrier and stores
+    uint32_t pn[II_RB][4];
+#pragma unroll
+    for (int r = 0; r < II_RB; r++) ii_pixels<VEC>(a, y0 + r, r < rows, x, pn[r]);
     for (int r0 = 0; r0 < rows; r0 += II_RB) {
       uint32_t q[II_RB][4];
 #pragma unroll
       for (int r = 0; r < II_RB; r++) {
-        uint32_t p[4];
-        if (r0 + r < rows) ii_pixels(a, y0 + r0 + r, x, p);
-        else p[0] = p[1] = p[2] = p[3] = 0u;
 #pragma unroll
-        for (int j = 0; j < 4; j++) c[j] += p[j];
+        for (int j = 0; j < 4; j++) c[j] += pn[r][j];
         q[r][0] = c[0];
         q[r][1] = q[r][0] + c[1];
         q[r][2] = q[r][1] + c[2];
@@ -189,6 +219,11 @@ __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
         for (int j = 0; j < 4; j++) q[r][j] += excl;
         if (l == 31) s_wt[buf][r][w] = incl;
       }
+#pragma unroll
+      for (int r = 0; r < II_RB; r++) {
+        const int rr = r0 + II_RB + r;
+        ii_pixels<VEC>(a, y0 + rr, rr < rows, x, pn[r]);
+      }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < II_RB; r++) {
@@ -198,7 +233,7 @@ __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
         for (int k = 0; k < II_BT / 32; k++) off += k < w ? s_wt[buf][r][k] : 0u;
         const int64_t y = y0 + r0 + r;
         uint32_t *dst = a.sat + y * a.W + x;
-        if (a.vec) {
+        if constexpr (VEC) {
           if (x < a.W) st_stream4(dst, q[r][0] + off, q[r][1] + off, q[r][2] + off, q[r][3] + off);
         } else {
 #pragma unroll
@@ -255,14 +290,16 @@ extern "C" cox_status cox_integral_image(const uint8_t *img, int64_t height, int
   a.colsum = (uint32_t *)(w + L.colsum);
   a.rowsum = (uint32_t *)(w + L.rowsum);
   a.total = (uint32_t *)(w + L.total);
-  a.vec = width % 4 == 0 && ((uintptr_t)img & 3u) == 0 && aligned16(sat);
+  const bool vec = width % 4 == 0 && ((uintptr_t)img & 3u) == 0 && aligned16(sat);
+  auto reduce = vec ? k_ii_reduce<true> : k_ii_reduce<false>;
+  auto scan = vec ? k_ii_scan<true> : k_ii_scan<false>;
   hipStream_t hs = (hipStream_t)stream;
   const int64_t tiles = a.nb * a.ns;
-  const int g1 = persistent_grid((const void *)k_ii_reduce, II_BT, tiles, 0, 0, 8);
-  hipLaunchKernelGGL(k_ii_reduce, dim3(g1), dim3(II_BT), 0, hs, a);
+  const int g1 = persistent_grid((const void *)reduce, II_BT, tiles, 0, 0, 8);
+  hipLaunchKernelGGL(reduce, dim3(g1), dim3(II_BT), 0, hs, a);
   const int64_t gc = (width + 255) / 256;
   hipLaunchKernelGGL(k_ii_colscan, dim3((unsigned)(gc < 65536 ? gc : 65536)), dim3(256), 0, hs, a);
-  const int g3 = persistent_grid((const void *)k_ii_scan, II_BT, tiles, 0, 0, 8);
-  hipLaunchKernelGGL(k_ii_scan, dim3(g3), dim3(II_BT), 0, hs, a);
+  const int g3 = persistent_grid((const void *)scan, II_BT, tiles, 0, 0, 8);
+  hipLaunchKernelGGL(scan, dim3(g3), dim3(II_BT), 0, hs, a);
   return launch_status();
 }

