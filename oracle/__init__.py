@@ -74,6 +74,7 @@ def lib():
             "coxo_uniform_branch": (I, [P, P, I64, P]),
             "coxo_grid_exchange": (I, [I, I, I, P]),
             "coxo_tile_sort_kv_u32": (I, [P, P, P, P, I64]),
+            "coxo_group_sort_u32": (I, [P, P, I64, I]),
             "coxo_integral_image_u8": (I, [P, I64, I64, P]),
             "coxo_cg": (I, [P, P, P, I64, P, P, I, C.c_double, I, I, P, P]),
         }
@@ -218,6 +219,15 @@ def tile_sort_u32(keys, group=32):
     keys = _c(keys, np.uint32)
     out = np.empty_like(keys)
     _check(lib().coxo_tile_sort_u32(_p(keys), _p(out), keys.size, group), "tile_sort_u32")
+    return out
+
+
+def group_sort_u32(keys, G):
+    """Every group of G consecutive keys sorted ascending (unsigned); G a
+    power of two up to 4096."""
+    k = _c(keys, np.uint32)
+    out = np.empty_like(k)
+    _check(lib().coxo_group_sort_u32(_p(k), _p(out), k.size, int(G)), "group_sort_u32")
     return out
 
 

@@ -1195,6 +1195,46 @@ int coxo_tile_sort_u32(const uint32_t *keys, uint32_t *out, int64_t n, int G) {
   return run_blocks((n + 31) / 32, sort_block, &c);
 }
 
+/* group sort for groups larger than a warp (64 .. 4096 keys, sorted on the
+ * GPU by a network whose wider exchanges cross the two halves of a wave or
+ * go through shared memory): every group of G consecutive keys (a partial
+ * last group: its valid keys) ascending as unsigned.  The result is unique,
+ * so the oracle is the plain definition: a bottom-up merge sort per group. */
+typedef struct {
+  const uint32_t *keys;
+  uint32_t *out;
+  int64_t n;
+  int G;
+} gs_ctx;
+
+static void gs_block(void *p, int64_t g) {
+  gs_ctx *c = (gs_ctx *)p;
+  const int64_t e0 = (int64_t)c->G * g;
+  const int m = (int)(c->n - e0 < c->G ? c->n - e0 : c->G);
+  uint32_t a[4096], b[4096];
+  memcpy(a, c->keys + e0, (size_t)m * 4);
+  uint32_t *src = a, *dst = b;
+  for (int w = 1; w < m; w *= 2) {
+    for (int lo = 0; lo < m; lo += 2 * w) {
+      const int mid = lo + w < m ? lo + w : m, hi = lo + 2 * w < m ? lo + 2 * w : m;
+      int i = lo, j = mid, k = lo;
+      while (i < mid && j < hi) dst[k++] = src[i] <= src[j] ? src[i++] : src[j++];
+      while (i < mid) dst[k++] = src[i++];
+      while (j < hi) dst[k++] = src[j++];
+    }
+    uint32_t *t = src;
+    src = dst;
+    dst = t;
+  }
+  memcpy(c->out + e0, src, (size_t)m * 4);
+}
+
+int coxo_group_sort_u32(const uint32_t *keys, uint32_t *out, int64_t n, int G) {
+  if (n < 0 || G < 2 || G > 4096 || (G & (G - 1))) return COXO_ERR_INVALID;
+  gs_ctx c = {keys, out, n, G};
+  return run_blocks((n + G - 1) / G, gs_block, &c);
+}
+
 /* key-value tile sort: every group of 32 consecutive (key, value) pairs
  * (a partial last group: its valid pairs) in ascending unsigned key order,
  * pairs with equal keys in their original order (a stable sort: sorting by

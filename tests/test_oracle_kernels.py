@@ -182,6 +182,25 @@ def test_tile_sort_adversarial(oracle_mod):
         assert np.array_equal(o.tile_sort_u32(c), np.sort(c))
 
 
+@pytest.mark.parametrize("G", [2, 32, 64, 256, 1024, 4096])
+@pytest.mark.parametrize("n", [1, 63, 5000, 3 * 4096 + 1001])
+def test_group_sort_matches_numpy(oracle_mod, G, n):
+    g = np.random.default_rng(G + n)
+    keys = g.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+    keys[::7] = keys[0]  # ties
+    out = oracle_mod.group_sort_u32(keys, G)
+    for s in range(0, n, G):
+        assert np.array_equal(out[s:s + G], np.sort(keys[s:s + G]))
+    if G == 32:
+        assert np.array_equal(out, oracle_mod.tile_sort_u32(keys))
+
+
+def test_group_sort_rejects_bad_sizes(oracle_mod):
+    for G in (0, 3, 8192):
+        with pytest.raises(oracle_mod.OracleError):
+            oracle_mod.group_sort_u32(np.zeros(8, np.uint32), G)
+
+
 @pytest.mark.parametrize("n,kmax", [(32, 4), (32 * 1000, 8), (32 * 1000 + 17, 1 << 32), (31, 2), (1, 5)])
 def test_tile_sort_kv_is_the_stable_sort(oracle_mod, n, kmax):
     g = np.random.default_rng(n)
