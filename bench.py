@@ -114,7 +114,8 @@ def other_kernels(fg, reps=10):
     """The kernels outside the timed step, each timed on its own: the
     block reduce (2^20 int32), the masked warp operations at three
     densities, the dynamic groups and the tile reductions (2^26 int32),
-    the key-value tile sort (2^28 pairs), the integral image (8192 x 8192),
+    the key-value tile sort (2^28 pairs), the 64- and 1024-key group sorts
+    (2^28 keys), the integral image (8192 x 8192),
     and the precision
     variants over 2^28 elements (float32 and bfloat16, sum and dot, plain
     and TwoSum).  Their timing does not depend on the values, so the
@@ -158,6 +159,11 @@ def other_kernels(fg, reps=10):
     kv = torch.arange(n, dtype=torch.int32, device="cuda")
     ok_, ov_ = torch.empty_like(kk), torch.empty_like(kv)
     res["tile_sort_kv_2p28"] = _entry(n, 16 * n, _timed(lambda: cox.tile_sort_kv(kk, kv, None, ok_, ov_), reps))
+    # wider groups: 64 keys over a full wave (one key per lane) and 1024 keys
+    # over four waves (four keys per lane), 8 bytes per key
+    for kpl, tile in ((1, 64), (4, 1024)):
+        res[f"group_sort_t{tile}_k{kpl}_2p28"] = _entry(
+            n, 8 * n, _timed(lambda: cox.tile_sort(kk, tile=tile, cfg=(kpl, 0), out=ok_), reps))
     del kk, kv, ok_, ov_
     # integral image of the 8192 x 8192 uint8 image: 1 byte read and 4
     # written per pixel

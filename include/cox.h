@@ -212,11 +212,16 @@ cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg 
 cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t *count,
                               const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
 
-/* Sorts every group of `tile` = 32 consecutive keys ascending (unsigned)
- * with a bitonic network whose cross-lane steps are __shfl_xor_sync
- * exchanges inside the group (cfg->items_per_lane keys per lane, 1 to 16;
- * 0 = default).  A partial last group is sorted among its valid keys.
- * keys, out: uint32[n] device buffers (may be the same buffer). */
+/* Sorts every group of `tile` consecutive keys ascending (unsigned) with a
+ * bitonic network.  tile = 32: the cross-lane steps are __shfl_xor_sync
+ * exchanges inside the group, cfg->items_per_lane keys per lane (1, 2, 4,
+ * 8 or 16; 0 = 4).  tile = 64 .. 1024 (a power of two): the group spans
+ * both halves of a wave (exchanges across them by v_permlane32_swap) or
+ * several waves (exchanges through shared memory); items_per_lane 4
+ * (0 = 4) for tile <= 1024, or 1 for tile <= 256 (tile 64 with 1 key per
+ * lane is the full-wave 64-key sort).  Other combinations give
+ * COX_ERR_UNSUPPORTED.  A partial last group is sorted among its valid
+ * keys.  keys, out: uint32[n] device buffers (may be the same buffer). */
 cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
                          const cox_cfg *cfg, void *stream);
 

@@ -1,63 +1,102 @@
-// 32-key bitonic tile sort.
+// Bitonic tile sort of groups of T = 32 .. 1024 keys.
 //
-// A group of 32 consecutive keys lives in LG = 32/K consecutive lanes of a
-// logical warp, K keys per lane (lane g of the group holds keys gK..gK+K-1,
-// loaded as one vector), so key index i = g*K + r.  The network is the
-// bitonic sorter in its all-ascending form: for each merge size k2 = 2, 4,
-// .., 32 a first layer compares i with i ^ (k2 - 1) (the mirror inside the
-// k2-block), then half-cleaner layers compare i with i ^ j for j = k2/4 ..
-// 1; the smaller index always keeps the minimum.  A layer whose partner
-// differs only in the low log2(K) bits is a compare-exchange between two
-// registers of one lane; every other layer is a __shfl_xor_sync inside the
-// group (partner lane g ^ (mask / K), register r ^ (mask mod K)) followed by
-// min or max.  With K = 4 all cross-lane layers are DPP quad_perm /
-// row_half_mirror exchanges.  The sorted result is the unique ascending
-// order, so any such network gives the same output as the one-key-per-lane
-// network.
+// A group of T consecutive keys lives in LG = T/K consecutive lanes, K keys
+// per lane (lane g of the group holds keys gK..gK+K-1, loaded as one
+// vector), so key index i = g*K + r.  The network is the bitonic sorter in
+// its all-ascending form: for each merge size k2 = 2, 4, .., T a first
+// layer compares i with i ^ (k2 - 1) (the mirror inside the k2-block), then
+// half-cleaner layers compare i with i ^ j for j = k2/4 .. 1; the smaller
+// index always keeps the minimum.  A layer whose partner differs only in
+// the low log2(K) bits is a compare-exchange between two registers of one
+// lane; every other layer exchanges with partner lane g ^ (mask / K),
+// register r ^ (mask mod K), then keeps min or max:
+//   - partner in the same 32-lane half: a __shfl_xor_sync (DPP or
+//     ds_swizzle; with K = 4 and T = 32 all are DPP quad_perm /
+//     row_half_mirror exchanges);
+//   - partner in the other half of the wave (a group of 64 lanes, the
+//     full-wave sort): the in-half exchange, then v_permlane32_swap;
+//   - partner in another wave (groups wider than a wave, the multi-warp
+//     sort): through shared memory, between two block barriers.
+// The sorted result is the unique ascending order, so any such network
+// gives the same output as a one-key-per-lane network.
 #include "cox_internal.hpp"
 
 namespace cox {
 
-template <int K, int PM, int LB>
-__device__ __forceinline__ void cx_layer(uint32_t (&key)[K], int g) {
+// value of lane t ^ LM of the wave (LM < 64)
+template <int LM>
+__device__ __forceinline__ uint32_t xor_lane_wave(uint32_t v) {
+  if constexpr (LM < 32) {
+    return (uint32_t)xor_lane<LM>((int)v);
+  } else {
+    const uint32_t u = LM == 32 ? v : (uint32_t)xor_lane<LM - 32>((int)v);
+    // swaps the upper half of the first operand with the lower half of the
+    // second: every lane receives the other half's value
+    const auto pr = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return lhalf() ? (uint32_t)pr[0] : (uint32_t)pr[1];
+  }
+}
+
+template <int K, int PM, int LB, int U>
+__device__ __forceinline__ void cx_layer(uint32_t (&key)[U][K], int g, uint32_t *lds) {
   constexpr int RM = PM & (K - 1);  // register part of the partner mask
   constexpr int LM = PM / K;        // lane part
   if constexpr (LM == 0) {
 #pragma unroll
-    for (int r = 0; r < K; r++) {
-      const int r2 = r ^ RM;
-      if (r < r2) {
-        const uint32_t a = key[r], b = key[r2];
-        key[r] = a < b ? a : b;
-        key[r2] = a < b ? b : a;
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int r = 0; r < K; r++) {
+        const int r2 = r ^ RM;
+        if (r < r2) {
+          const uint32_t a = key[u][r], b = key[u][r2];
+          key[u][r] = a < b ? a : b;
+          key[u][r2] = a < b ? b : a;
+        }
       }
-    }
   } else {
     // the lower lane of a pair keeps min = med3(a, b, 0), the upper one
     // max = med3(a, b, ~0): one exchange and one median per key
-    uint32_t other[K];
-#pragma unroll
-    for (int r = 0; r < K; r++) other[r] = (uint32_t)xor_lane<LM>((int)key[r ^ RM]);
     const uint32_t sel = (g & (LB / K)) ? 0xffffffffu : 0u;
+    uint32_t other[U][K];
+    if constexpr (LM < 64) {
 #pragma unroll
-    for (int r = 0; r < K; r++) key[r] = med3u(key[r], other[r], sel);
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int r = 0; r < K; r++) other[u][r] = xor_lane_wave<LM>(key[u][r ^ RM]);
+    } else {
+      const int t = threadIdx.x;
+#pragma unroll
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int r = 0; r < K; r++) lds[(u * 256 + t) * K + r] = key[u][r];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U; u++)
+#pragma unroll
+        for (int r = 0; r < K; r++) other[u][r] = lds[u * 256 * K + ((t * K + r) ^ PM)];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++)
+#pragma unroll
+      for (int r = 0; r < K; r++) key[u][r] = med3u(key[u][r], other[u][r], sel);
   }
 }
 
-template <int K, int K2, int J>
-__device__ __forceinline__ void half_cleaners(uint32_t (&key)[K], int g) {
+template <int K, int J, int U>
+__device__ __forceinline__ void half_cleaners(uint32_t (&key)[U][K], int g, uint32_t *lds) {
   if constexpr (J >= 1) {
-    cx_layer<K, J, J>(key, g);
-    half_cleaners<K, K2, J / 2>(key, g);
+    cx_layer<K, J, J, U>(key, g, lds);
+    half_cleaners<K, J / 2, U>(key, g, lds);
   }
 }
 
-template <int K, int K2>
-__device__ __forceinline__ void merge_stages(uint32_t (&key)[K], int g) {
-  if constexpr (K2 <= 32) {
-    cx_layer<K, K2 - 1, K2 / 2>(key, g);  // mirror layer
-    half_cleaners<K, K2, K2 / 4>(key, g);
-    merge_stages<K, K2 * 2>(key, g);
+template <int K, int K2, int T, int U>
+__device__ __forceinline__ void merge_stages(uint32_t (&key)[U][K], int g, uint32_t *lds) {
+  if constexpr (K2 <= T) {
+    cx_layer<K, K2 - 1, K2 / 2, U>(key, g, lds);  // mirror layer
+    half_cleaners<K, K2 / 4, U>(key, g, lds);
+    merge_stages<K, K2 * 2, T, U>(key, g, lds);
   }
 }
 
@@ -93,14 +132,20 @@ __device__ __forceinline__ void store_keys(uint32_t *__restrict__ p, const uint3
 // Grid-stride rounds; in a round a block handles U rows of 256 lane
 // vectors (row u = vectors [base + 256u, base + 256u + 256)), and each
 // thread first requests its U vectors, then sorts and stores them, so U
-// independent loads per lane are in flight.  Every 32-key group is held by
-// LG lanes of one logical warp (groups never straddle a warp since
-// 32 | 32K).  keys and out may be the same buffer (each lane writes back
-// only the positions it read, after its whole group has been sorted).
-template <int K>
+// independent loads per lane are in flight.  Every group is held by LG
+// aligned lanes of one block row (T <= 256 K).  keys and out may be the
+// same buffer (each lane writes back only the positions it read, after its
+// whole group has been sorted).
+template <int K, int T>
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n) {
-  constexpr int LG = 32 / K;
+  constexpr int LG = T / K;
+  static_assert(LG >= 1 && LG <= 256, "a group fits in one block row");
   constexpr int U = K >= 16 ? 1 : 16 / K > 4 ? 4 : 16 / K;
+  uint32_t *lds = nullptr;
+  if constexpr (LG > 64) {
+    __shared__ uint32_t s_x[U * 256 * K];  // the exchanges between waves
+    lds = s_x;
+  }
   const int g = (int)(threadIdx.x % LG);
   const int64_t nvec = (n + K - 1) / K;
   const int64_t per_round = (int64_t)gridDim.x * 256 * U;
@@ -121,8 +166,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t *keys, uint32_
         for (int r = 0; r < K; r++) key[u][r] = e0 + r < n ? keys[e0 + r] : 0xffffffffu;
       }
     }
-#pragma unroll
-    for (int u = 0; u < U; u++) merge_stages<K, 2>(key[u], g);
+    merge_stages<K, 2, T, U>(key, g, lds);
     if (full) {
 #pragma unroll
       for (int u = 0; u < U; u++) store_keys<K>(out + (vbase + 256 * u) * K, key[u]);
@@ -251,13 +295,29 @@ __global__ __launch_bounds__(256) void k_tile_sort_kv(const uint32_t *keys, cons
 }
 
 using sort_fn = void (*)(const uint32_t *, uint32_t *, int64_t);
-static sort_fn pick_sort(int k) {
-  switch (k) {
-  case 1: return k_tile_sort<1>;
-  case 2: return k_tile_sort<2>;
-  case 4: return k_tile_sort<4>;
-  case 8: return k_tile_sort<8>;
-  case 16: return k_tile_sort<16>;
+static sort_fn pick_sort(int k, int tile) {
+  if (tile == 32) {
+    switch (k) {
+    case 1: return k_tile_sort<1, 32>;
+    case 2: return k_tile_sort<2, 32>;
+    case 4: return k_tile_sort<4, 32>;
+    case 8: return k_tile_sort<8, 32>;
+    case 16: return k_tile_sort<16, 32>;
+    }
+  } else if (k == 1) {
+    switch (tile) {
+    case 64: return k_tile_sort<1, 64>;
+    case 128: return k_tile_sort<1, 128>;
+    case 256: return k_tile_sort<1, 256>;
+    }
+  } else if (k == 4) {
+    switch (tile) {
+    case 64: return k_tile_sort<4, 64>;
+    case 128: return k_tile_sort<4, 128>;
+    case 256: return k_tile_sort<4, 256>;
+    case 512: return k_tile_sort<4, 512>;
+    case 1024: return k_tile_sort<4, 1024>;
+    }
   }
   return nullptr;
 }
@@ -279,10 +339,10 @@ using namespace cox;
 
 extern "C" cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
                                     const cox_cfg *cfg, void *stream) {
-  if (n < 0 || tile != 32) return COX_ERR_INVALID;
+  if (n < 0 || tile < 32 || tile > 1024 || (tile & (tile - 1))) return COX_ERR_INVALID;
   const int k = (cfg && cfg->items_per_lane) ? cfg->items_per_lane : 4;
   if (cfg && cfg->grid_blocks < 0) return COX_ERR_INVALID;
-  sort_fn fn = pick_sort(k);
+  sort_fn fn = pick_sort(k, tile);
   if (!fn) return k > 0 && k <= 32 && (k & (k - 1)) == 0 ? COX_ERR_UNSUPPORTED : COX_ERR_INVALID;
   if (n == 0) return COX_OK;
   if (!keys || !out) return COX_ERR_INVALID;
