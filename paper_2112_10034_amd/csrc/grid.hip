@@ -258,39 +258,74 @@ __device__ __forceinline__ uint32_t col_at(const CgArgs &a, int32_t jj) {
   return j < (uint32_t)a.n ? j : (uint32_t)a.n - 1u;
 }
 
-// (A v)_i for the R rows of a thread, the rows' entries stepped together
-// so that the R rows' loads are in flight at once; each row accumulates in
-// storage order from +0.0f with fmaf.  vj(j) gives v_j.
-template <int R, class V>
-__device__ __forceinline__ void spmv_rows(const CgArgs &a, const int32_t (&row)[R], float (&acc)[R], V vj) {
-  int32_t lo[R], hi[R];
-  int32_t len = 0;
+// (A v)_i for the R rows of a thread, each row accumulating its entries
+// in storage order from +0.0f with fmaf.  The CSR work is fetched ahead:
+// fetch_bounds requests the rows' bounds, fetch_entries the next SU
+// entries of every row at once (so a row of up to SU entries costs one
+// round trip, and callers issue both before unrelated loads and barriers),
+// and spmv_finish consumes them, gathering v_j through vj.
+// SU entries per row and fetch, as deep as registers allow without spills:
+// 4 (2 for R = 8) in the streaming kernels, 2 (1 for R = 8) in the kernel
+// that keeps x, r, p and q resident
+template <int R>
+constexpr int su_stream() {
+  return R >= 8 ? 2 : 4;
+}
+template <int R>
+constexpr int su_resident() {
+  return R >= 8 ? 1 : 2;
+}
+template <int R, int SU>
+struct RowFetch {
+  int32_t lo[R], hi[R], len;
+  uint32_t j[SU][R];
+  float v[SU][R];
+};
+
+template <int R, int SU>
+__device__ __forceinline__ void fetch_bounds(const CgArgs &a, const int32_t (&row)[R], RowFetch<R, SU> &f) {
+  f.len = 0;
 #pragma unroll
   for (int q = 0; q < R; q++) {
-    acc[q] = 0.0f;
     if (row[q] < a.n) {
-      row_bounds(a, row[q], lo[q], hi[q]);
+      row_bounds(a, row[q], f.lo[q], f.hi[q]);
     } else {
-      lo[q] = 0;
-      hi[q] = 0;
+      f.lo[q] = 0;
+      f.hi[q] = 0;
     }
-    len = max(len, hi[q] - lo[q]);
+    f.len = max(f.len, f.hi[q] - f.lo[q]);
   }
-  for (int32_t s = 0; s < len; s++) {
-    uint32_t j[R];
-    float v[R];
+}
+
+template <int R, int SU>
+__device__ __forceinline__ void fetch_entries(const CgArgs &a, int32_t s0, RowFetch<R, SU> &f) {
+#pragma unroll
+  for (int u = 0; u < SU; u++)
 #pragma unroll
     for (int q = 0; q < R; q++) {
-      const bool ok = lo[q] + s < hi[q];
-      j[q] = ok ? col_at(a, lo[q] + s) : 0u;
-      v[q] = ok ? a.val[lo[q] + s] : 0.0f;
+      const int32_t k = f.lo[q] + s0 + u;
+      const bool ok = k < f.hi[q];
+      f.j[u][q] = ok ? col_at(a, k) : 0u;
+      f.v[u][q] = ok ? a.val[k] : 0.0f;
     }
-    float g[R];
+}
+
+template <int R, int SU, class V>
+__device__ __forceinline__ void spmv_finish(const CgArgs &a, RowFetch<R, SU> &f, float (&acc)[R], V vj) {
 #pragma unroll
-    for (int q = 0; q < R; q++) g[q] = lo[q] + s < hi[q] ? vj(j[q]) : 0.0f;
+  for (int q = 0; q < R; q++) acc[q] = 0.0f;
+  for (int32_t s0 = 0; s0 < f.len; s0 += SU) {
+    if (s0) fetch_entries(a, s0, f);
+    float g[SU][R];
 #pragma unroll
-    for (int q = 0; q < R; q++)
-      if (lo[q] + s < hi[q]) acc[q] = __builtin_fmaf(v[q], g[q], acc[q]);
+    for (int u = 0; u < SU; u++)
+#pragma unroll
+      for (int q = 0; q < R; q++) g[u][q] = f.lo[q] + s0 + u < f.hi[q] ? vj(f.j[u][q]) : 0.0f;
+#pragma unroll
+    for (int u = 0; u < SU; u++)
+#pragma unroll
+      for (int q = 0; q < R; q++)
+        if (f.lo[q] + s0 + u < f.hi[q]) acc[q] = __builtin_fmaf(f.v[u][q], g[u][q], acc[q]);
   }
 }
 
@@ -330,12 +365,15 @@ __device__ __forceinline__ int32_t cg_window(const CgArgs &a, int64_t c, bool fi
 }
 
 // r = b - A x, partials of <r, r>; the resident form keeps x and r
-template <int R, int W, class SH>
+template <int R, int W, int SU, class SH>
 __device__ __forceinline__ void cg_phase0_chunk(const CgArgs &a, int64_t c, SH &sh, float (&xv)[R], float (&rv)[R]) {
   int32_t row[R];
   float ax[R];
   rows_of<R, W>(c, row);
-  spmv_rows<R>(a, row, ax, [&](uint32_t j) { return a.x[j]; });
+  RowFetch<R, SU> f;
+  fetch_bounds(a, row, f);
+  fetch_entries(a, 0, f);
+  spmv_finish(a, f, ax, [&](uint32_t j) { return a.x[j]; });
   double s = -0.0;
 #pragma unroll
   for (int q = 0; q < R; q++) {
@@ -352,17 +390,22 @@ __device__ __forceinline__ void cg_phase0_chunk(const CgArgs &a, int64_t c, SH &
 }
 
 // p (into p[k & 1]) and q = A p, partials of <p, q>
-template <int R, int W, class SH>
+template <int R, int W, int SU, class SH>
 __device__ __forceinline__ void cg_phase1_chunk(const CgArgs &a, int64_t c, int k, float beta, SH &sh, float (&pv)[R],
                                                 float (&qv)[R]) {
   const bool first = k == 0;
   const float *pp = a.p[(k + 1) & 1];
   float *pn = a.p[k & 1];
-  int32_t wn;
-  const int32_t w0 = cg_window<R, W>(a, c, first, beta, pp, sh, wn);
+  // the rows' CSR bounds and first entries are requested before the
+  // window's loads and barrier
   int32_t row[R];
   rows_of<R, W>(c, row);
-  spmv_rows<R>(a, row, qv, [&](uint32_t j) {
+  RowFetch<R, SU> f;
+  fetch_bounds(a, row, f);
+  fetch_entries(a, 0, f);
+  int32_t wn;
+  const int32_t w0 = cg_window<R, W>(a, c, first, beta, pp, sh, wn);
+  spmv_finish(a, f, qv, [&](uint32_t j) {
     const uint32_t o = j - (uint32_t)w0;
     if (o < (uint32_t)wn) return sh.win[o];
     const float rj = ldcf(a.r + j);
@@ -406,7 +449,7 @@ template <int R, int W, class SH>
 __device__ void cg_phase0(const CgArgs &a, SH &sh) {
   for (int64_t c = blockIdx.x; c < a.nch; c += gridDim.x) {
     float xv[R], rv[R];
-    cg_phase0_chunk<R, W>(a, c, sh, xv, rv);
+    cg_phase0_chunk<R, W, su_stream<R>()>(a, c, sh, xv, rv);
   }
 }
 
@@ -414,7 +457,7 @@ template <int R, int W, class SH>
 __device__ void cg_phase1(const CgArgs &a, int k, float beta, SH &sh) {
   for (int64_t c = blockIdx.x; c < a.nch; c += gridDim.x) {
     float pv[R], qv[R];
-    cg_phase1_chunk<R, W>(a, c, k, beta, sh, pv, qv);
+    cg_phase1_chunk<R, W, su_stream<R>()>(a, c, k, beta, sh, pv, qv);
     int32_t row[R];
     rows_of<R, W>(c, row);
 #pragma unroll
@@ -496,7 +539,7 @@ __global__ __launch_bounds__(32 * W) void k_cg_res(CgArgs a) {
   const bool own = c < a.nch;  // uniform over the block
   float xv[R], rv[R], pv[R], qv[R];
   int32_t k = 0, reason = CG_ABORTED;
-  if (own) cg_phase0_chunk<R, W>(a, c, sh, xv, rv);
+  if (own) cg_phase0_chunk<R, W, su_resident<R>()>(a, c, sh, xv, rv);
   if (grid_sync(a.bar, a.hdr)) {
     double rr = final64(a.prr, a.nch, sh), rr_prev = 0.0;
     for (;; k++) {
@@ -509,7 +552,7 @@ __global__ __launch_bounds__(32 * W) void k_cg_res(CgArgs a) {
         reason = CG_MAX_ITER;
         break;
       }
-      if (own) cg_phase1_chunk<R, W>(a, c, k, k ? (float)(rr / rr_prev) : 0.0f, sh, pv, qv);
+      if (own) cg_phase1_chunk<R, W, su_resident<R>()>(a, c, k, k ? (float)(rr / rr_prev) : 0.0f, sh, pv, qv);
       if (!grid_sync(a.bar, a.hdr)) break;
       const double pq = final64(a.ppq, a.nch, sh);
       if (!(pq > 0.0)) {
