@@ -26,7 +26,12 @@ namespace cox {
 constexpr int II_TH = 64;     // rows per tile
 constexpr int II_TW = 1024;   // columns per tile
 constexpr int II_BT = 256;    // threads per block, 4 columns each
-constexpr int II_RB = 8;      // rows per shared-memory round
+constexpr int II_RB = 8;      // rows per round of the reduce kernel (its butterfly sums 8)
+constexpr int II_RS = 4;      // rows per shared-memory round of the scan kernel (measured: 4 rows
+                              // 93 us, 8 rows 99 us, 16 rows 106 us at 8192 x 8192)
+// wave 0 (64 threads) handles the tile's rows: one row per thread, two
+// logical warps
+static_assert(II_TH == 64 && II_BT >= 64 && II_TW == 4 * II_BT, "tile shape the kernels assume");
 
 // inclusive scan over the 32 lanes of a logical warp
 __device__ __forceinline__ uint32_t ii_warp_scan(uint32_t v) {
@@ -166,7 +171,7 @@ template <bool VEC>
 __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
   __shared__ uint32_t s_lin[II_TH];             // row carries, prefixed inside each 32-row half
   __shared__ uint32_t s_left[II_TH];            // corner + row carries, prefixed over the tile's rows
-  __shared__ uint32_t s_wt[2][II_RB][II_BT / 32];  // warp totals of a round of rows
+  __shared__ uint32_t s_wt[2][II_RS][II_BT / 32];  // warp totals of a round of rows
   __shared__ uint32_t s_red[II_BT / 32];
   const int t = threadIdx.x, w = t >> 5, l = t & 31;
   int buf = 0;
@@ -198,15 +203,15 @@ __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
       s_left[t] = corner + s_lin[t] + (t >= 32 ? s_lin[31] : 0u);
     }
     __syncthreads();
-    // rounds of II_RB rows; the next round's pixels are requested before
+    // rounds of II_RS rows; the next round's pixels are requested before
     // the current round's barrier and stores
-    uint32_t pn[II_RB][4];
+    uint32_t pn[II_RS][4];
 #pragma unroll
-    for (int r = 0; r < II_RB; r++) ii_pixels<VEC>(a, y0 + r, r < rows, x, pn[r]);
-    for (int r0 = 0; r0 < rows; r0 += II_RB) {
-      uint32_t q[II_RB][4];
+    for (int r = 0; r < II_RS; r++) ii_pixels<VEC>(a, y0 + r, r < rows, x, pn[r]);
+    for (int r0 = 0; r0 < rows; r0 += II_RS) {
+      uint32_t q[II_RS][4];
 #pragma unroll
-      for (int r = 0; r < II_RB; r++) {
+      for (int r = 0; r < II_RS; r++) {
 #pragma unroll
         for (int j = 0; j < 4; j++) c[j] += pn[r][j];
         q[r][0] = c[0];
@@ -220,13 +225,13 @@ __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
         if (l == 31) s_wt[buf][r][w] = incl;
       }
 #pragma unroll
-      for (int r = 0; r < II_RB; r++) {
-        const int rr = r0 + II_RB + r;
+      for (int r = 0; r < II_RS; r++) {
+        const int rr = r0 + II_RS + r;
         ii_pixels<VEC>(a, y0 + rr, rr < rows, x, pn[r]);
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < II_RB; r++) {
+      for (int r = 0; r < II_RS; r++) {
         if (r0 + r >= rows) break;
         uint32_t off = s_left[r0 + r];
 #pragma unroll
