@@ -405,6 +405,14 @@ cox_status cox_grid_capacity(int32_t *max_blocks);
  * grid_blocks, 0, NULL). */
 cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out, void *ws, size_t ws_bytes,
                              void *stream);
+/* Check of the barrier's failure handling: the exchange kernel with block
+ * absent_block (0 <= absent_block < grid_blocks) leaving before the first
+ * barrier, and every wait bounded by spin_limit polls (1 .. 2^20) instead
+ * of the usual bound.  The other blocks' waits give up, every block
+ * finishes, and cox_workspace_status then reports COX_ERR_TIMEOUT; out is
+ * meaningless.  The next call on the workspace starts clean. */
+cox_status cox_grid_exchange_absent(int32_t grid_blocks, int32_t rounds, int32_t absent_block, uint32_t spin_limit,
+                                    uint32_t *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Conjugate gradient (Hestenes and Stiefel) for A x = b, A symmetric
  * positive definite in CSR form, in ONE cooperative launch: the iteration

@@ -78,6 +78,7 @@ _SIGS = {
     "cox_integral_image": (_I, [_P, _I64, _I64, _P, _P, _SZ, _P]),
     "cox_grid_capacity": (_I, [C.POINTER(C.c_int32)]),
     "cox_grid_exchange": (_I, [C.c_int32, C.c_int32, _P, _P, _SZ, _P]),
+    "cox_grid_exchange_absent": (_I, [C.c_int32, C.c_int32, C.c_int32, C.c_uint32, _P, _P, _SZ, _P]),
     "cox_cg_solve": (_I, [_P, _P, _P, _I64, _I64, _P, _P, C.c_int32, C.c_double, _P, _P, C.POINTER(cox_cfg), _P,
                           _SZ, _P]),
     "cox_cg_solve_per_phase": (_I, [_P, _P, _P, _I64, _I64, _P, _P, C.c_int32, C.c_double, _P, _P,
@@ -400,6 +401,18 @@ def grid_exchange(grid_blocks, rounds, out=None):
            "cox_grid_exchange")
     ws.status()
     return out
+
+
+def grid_exchange_absent(grid_blocks, rounds, absent_block, spin_limit):
+    """The exchange kernel with one block absent from the first barrier and
+    a small spin bound: returns the workspace status afterwards (expected
+    COX_ERR_TIMEOUT); synchronises."""
+    out = torch.empty((grid_blocks, 1024), dtype=torch.int32, device="cuda")
+    ws = workspace(OP_GRID_EXCHANGE, U32, grid_blocks)
+    _check(lib().cox_grid_exchange_absent(int(grid_blocks), int(rounds), int(absent_block), int(spin_limit),
+                                          _ptr(out), _ptr(ws.tensor), ws.nbytes, _stream()),
+           "cox_grid_exchange_absent")
+    return lib().cox_workspace_status(_ptr(ws.tensor), _stream())
 
 
 def cg_solve(row_ptr, col_idx, val, b, x, max_iter, tol=0.0, cfg=None, rr_hist=None, result=None,

@@ -75,7 +75,7 @@ __device__ __forceinline__ void wait_stores() { asm volatile("s_waitcnt vmcnt(0)
 // device-coherent writes of all blocks before it are visible to the
 // device-coherent reads of all blocks after it.  false: the wait gave up,
 // and the kernel should finish without further barriers.
-__device__ bool grid_sync(uint32_t *bar, uint32_t *hdr) {
+__device__ bool grid_sync(uint32_t *bar, uint32_t *hdr, uint32_t spin_limit = GRID_MAX_SPIN) {
   __shared__ uint32_t s_ok;
   wait_stores();
   __syncthreads();
@@ -103,7 +103,7 @@ __device__ bool grid_sync(uint32_t *bar, uint32_t *hdr) {
     if (!released) {
       uint32_t spins = 0;
       while (ldc32(&bar[GB_GEN]) == gen) {
-        if (ldc32(&bar[GB_ABORT]) != 0u || ++spins > GRID_MAX_SPIN) {
+        if (ldc32(&bar[GB_ABORT]) != 0u || ++spins > spin_limit) {
           stc32(&bar[GB_ABORT], 1u);
           stc32(&hdr[HDR_ERR], 1u);
           ok = 0u;
@@ -136,17 +136,20 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
 constexpr int GX_BLOCK = 1024;
 
 // round r: write own row, barrier, add the row of block (b + r + 1) mod G,
-// barrier
+// barrier.  Failure-handling check: block `absent` (-1: none) leaves before
+// the first barrier, so the other blocks' waits give up after spin_limit
+// polls and every block finishes.
 __global__ __launch_bounds__(GX_BLOCK) void k_grid_exchange(uint32_t *slot, uint32_t *out, int rounds, uint32_t *bar,
-                                                            uint32_t *hdr) {
+                                                            uint32_t *hdr, int absent, uint32_t spin_limit) {
   const uint32_t G = gridDim.x, b = blockIdx.x, t = threadIdx.x;
   uint32_t sum = 0u;
   for (int r = 0; r < rounds; r++) {
     stc32(&slot[(size_t)b * GX_BLOCK + t], fmix32(((uint32_t)r << 20) ^ (b << 10) ^ t));
-    if (!grid_sync(bar, hdr)) break;
+    if ((int)b == absent) break;
+    if (!grid_sync(bar, hdr, spin_limit)) break;
     const uint32_t src = (uint32_t)(((uint64_t)b + (uint64_t)r + 1u) % G);
     sum += ldc32(&slot[(size_t)src * GX_BLOCK + t]);
-    if (!grid_sync(bar, hdr)) break;
+    if (!grid_sync(bar, hdr, spin_limit)) break;
   }
   out[(size_t)b * GX_BLOCK + t] = sum;
 }
@@ -779,8 +782,8 @@ cox_status cox_grid_capacity(int32_t *max_blocks) {
   return launch_status();
 }
 
-cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out, void *ws, size_t ws_bytes,
-                             void *stream) {
+static cox_status gx_run(int32_t grid_blocks, int32_t rounds, int absent, uint32_t spin_limit, uint32_t *out, void *ws,
+                        size_t ws_bytes, void *stream) {
   if (grid_blocks < 1 || rounds < 0 || !out) return COX_ERR_INVALID;
   if (grid_blocks > blocks_per_cu((const void *)k_grid_exchange, GX_BLOCK) * device_cus()) return COX_ERR_INVALID;
   if (!ws || ws_bytes < gx_workspace_bytes(grid_blocks)) return COX_ERR_WORKSPACE;
@@ -792,7 +795,7 @@ cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out,
   hipLaunchKernelGGL(k_grid_clear, dim3(1), dim3(256), 0, hs, bar, (int)(GB_BYTES / 4));
   cox_status st = launch_status();
   if (st != COX_OK) return st;
-  void *args[] = {&slot, &out, &rounds, &bar, &hdr};
+  void *args[] = {&slot, &out, &rounds, &bar, &hdr, &absent, &spin_limit};
   const hipError_t e = hipLaunchCooperativeKernel((const void *)k_grid_exchange, dim3(grid_blocks), dim3(GX_BLOCK),
                                                   args, 0, hs);
   if (e != hipSuccess) {
@@ -800,6 +803,18 @@ cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out,
     return COX_ERR_HIP;
   }
   return COX_OK;
+}
+
+cox_status cox_grid_exchange(int32_t grid_blocks, int32_t rounds, uint32_t *out, void *ws, size_t ws_bytes,
+                             void *stream) {
+  return gx_run(grid_blocks, rounds, -1, GRID_MAX_SPIN, out, ws, ws_bytes, stream);
+}
+
+cox_status cox_grid_exchange_absent(int32_t grid_blocks, int32_t rounds, int32_t absent_block, uint32_t spin_limit,
+                                    uint32_t *out, void *ws, size_t ws_bytes, void *stream) {
+  if (absent_block < 0 || absent_block >= grid_blocks || spin_limit < 1 || spin_limit > GRID_MAX_SPIN)
+    return COX_ERR_INVALID;
+  return gx_run(grid_blocks, rounds, absent_block, spin_limit, out, ws, ws_bytes, stream);
 }
 
 }  // extern "C"

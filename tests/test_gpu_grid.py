@@ -50,6 +50,28 @@ def test_grid_exchange_rejects_oversized_grid(dev):
     assert e.value.code == 1
 
 
+@pytest.mark.parametrize("G,absent", [(8, 3), (64, 0), (0, 511)])
+def test_grid_barrier_gives_up_when_a_block_is_absent(dev, oracle_mod, G, absent):
+    """Failure handling forced from the host: one block never arrives and the
+    waits are bounded by 2000 polls, so every block finishes, the workspace
+    reports COX_ERR_TIMEOUT, and the next call on it is correct."""
+    torch, cox = dev
+    G = cox.grid_capacity() if G == 0 else G
+    absent = min(absent, G - 1)
+    print("grid exchange with block", absent, "of", G, "absent", flush=True)
+    assert cox.grid_exchange_absent(G, 4, absent, 2000) == cox.ERR_TIMEOUT
+    got = cox.grid_exchange(G, 5).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, oracle_mod.grid_exchange(G, 5, block=1024))
+
+
+def test_grid_exchange_absent_rejects_bad_arguments(dev):
+    torch, cox = dev
+    for G, absent, spins in ((8, 8, 10), (8, -1, 10), (8, 0, 0), (8, 0, (1 << 20) + 1)):
+        with pytest.raises(cox.CoxError) as e:
+            cox.grid_exchange_absent(G, 1, absent, spins)
+        assert e.value.code == 1
+
+
 def _system(kind, n, seed):
     return inputs.cg_tridiag(n, seed=seed) if kind == "tri" else inputs.cg_irregular(n, seed=seed)
 
