@@ -81,3 +81,59 @@ def test_invalid_arguments_rejected_before_launch(cox):
     assert L.cox_warp_scan(C.c_void_p(16), C.c_void_p(16), 100, None, C.c_void_p(256), 8, None) == 5
     bad = cox.make_cfg(3, 8)
     assert L.cox_warp_scan(C.c_void_p(16), C.c_void_p(16), 100, C.byref(bad), None, 0, None) == 1
+
+
+def _up256(v):
+    return (v + 255) // 256 * 256
+
+
+def test_workspace_sizes_of_the_widened_operations(cox):
+    L = cox.lib()
+    assert cox.default_cfg(cox.OP_CG, cox.F32) == (4, 32, 0)
+    for n in (0, 1, 1000, 1 << 20):
+        S = 32 * 32 * 4
+        nch = -(-n // S)
+        want = 256 + 2048 + 256 + 4 * _up256(4 * n) + 2 * _up256(8 * nch)
+        assert L.cox_workspace_bytes(cox.OP_CG, cox.F32, n, 0, None) == want
+    for G in (1, 256):
+        assert L.cox_workspace_bytes(cox.OP_GRID_EXCHANGE, cox.U32, G, 0, None) == 256 + 2048 + 4096 * G
+    for H, W in ((1, 1), (65, 1025), (8192, 8192)):
+        nb, ns = -(-H // 64), -(-W // 1024)
+        want = 256 + _up256(4 * nb * W) + _up256(4 * ns * H) + _up256(4 * nb * ns)
+        assert L.cox_workspace_bytes(cox.OP_INTEGRAL_IMAGE, cox.U32, H, W, None) == want
+    assert L.cox_workspace_bytes(cox.OP_INTEGRAL_IMAGE, cox.U32, 4, -1, None) == 0
+
+
+def test_widened_entry_points_reject_bad_arguments_before_launch(cox):
+    L = cox.lib()
+    P = C.c_void_p
+    # tile sort: tiles that are not powers of two in [32, 1024], unsupported keys per lane
+    assert L.cox_tile_sort(None, None, 64, 48, None, None) == 1
+    assert L.cox_tile_sort(None, None, 64, 2048, None, None) == 1
+    assert L.cox_tile_sort(None, None, 64, 64, C.byref(cox.make_cfg(2, 0)), None) == 6
+    assert L.cox_tile_sort(None, None, 0, 1024, None, None) == 0
+    # key-value sort: size, tile, keys per lane, aliasing, alignment
+    assert L.cox_tile_sort_kv(None, None, None, None, -1, 32, None, None) == 1
+    assert L.cox_tile_sort_kv(None, None, None, None, 64, 64, None, None) == 1
+    assert L.cox_tile_sort_kv(None, None, None, None, 64, 32, C.byref(cox.make_cfg(16, 0)), None) == 6
+    assert L.cox_tile_sort_kv(P(16), P(256), P(32), P(256), 64, 32, None, None) == 1
+    assert L.cox_tile_sort_kv(P(16), P(256), P(36), P(512), 64, 32, None, None) == 3
+    # integral image: negative shape, empty image, missing buffers, small workspace
+    assert L.cox_integral_image(None, -1, 5, None, None, 0, None) == 1
+    assert L.cox_integral_image(None, 0, 5, None, None, 0, None) == 0
+    assert L.cox_integral_image(None, 5, 5, None, None, 0, None) == 1
+    assert L.cox_integral_image(P(16), 5, 5, P(16), P(256), 16, None) == 5
+    # grid exchange and its failure check
+    assert L.cox_grid_exchange(0, 1, P(16), None, 0, None) == 1
+    assert L.cox_grid_exchange(4, -1, P(16), None, 0, None) == 1
+    assert L.cox_grid_exchange_absent(4, 1, 4, 10, P(16), None, 0, None) == 1
+    assert L.cox_grid_exchange_absent(4, 1, 0, 0, P(16), None, 0, None) == 1
+    # conjugate gradient: sizes, missing result, schedules, workspace
+    cg = L.cox_cg_solve
+    args = (P(16), P(16), P(16), 100, 300, P(16), P(16), 5, C.c_double(0.0), P(16), None)
+    assert cg(P(16), P(16), P(16), -1, 0, P(16), P(16), 5, C.c_double(0.0), P(16), None, None, None, 0, None) == 1
+    assert cg(*args[:9], None, None, None, None, 0, None) == 1
+    assert cg(*args, C.byref(cox.make_cfg(4, 4)), P(256), 1 << 30, None) == 6
+    assert cg(*args, C.byref(cox.make_cfg(3, 32)), P(256), 1 << 30, None) == 1
+    assert cg(*args, None, P(256), 64, None) == 5
+    assert L.cox_cg_solve_per_phase(*args, None, P(256), 64, None) == 5
