@@ -29,15 +29,19 @@
 namespace cox {
 
 // all-reduce of v over the logical warp's 32 lanes for a commutative op
-// (every lane ends with the result): rotations inside the 16-lane rows,
-// then v_permlane16_swap of v with itself, which leaves every lane its own
-// row's value and the other row's, in one order or the other
-template <class F>
+// with identity ID (every lane ends with the result): rotations inside the
+// 16-lane rows, then v_permlane16_swap of v with itself, which leaves every
+// lane its own row's value and the other row's, in one order or the other.
+// The rotation is a DPP update whose old value is the identity: the
+// compiler folds it into the op (v_add_u32_dpp, v_min_i32_dpp, ...; a
+// plain DPP move would stay a separate instruction).  Row rotations read
+// no invalid lane, so the old value never shows.
+template <uint32_t ID, class F>
 __device__ __forceinline__ uint32_t allreduce32(uint32_t v, F op) {
-  v = op(v, (uint32_t)dpp_mov<0x128>((int)v));  // row_ror:8
-  v = op(v, (uint32_t)dpp_mov<0x124>((int)v));  // row_ror:4
-  v = op(v, (uint32_t)dpp_mov<0x122>((int)v));  // row_ror:2
-  v = op(v, (uint32_t)dpp_mov<0x121>((int)v));  // row_ror:1
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ID, (int)v, 0x128, 0xf, 0xf, false));  // row_ror:8
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ID, (int)v, 0x124, 0xf, 0xf, false));  // row_ror:4
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ID, (int)v, 0x122, 0xf, 0xf, false));  // row_ror:2
+  v = op(v, (uint32_t)__builtin_amdgcn_update_dpp((int)ID, (int)v, 0x121, 0xf, 0xf, false));  // row_ror:1
   const auto pr = __builtin_amdgcn_permlane16_swap(v, v, false, false);
   return op((uint32_t)pr[0], (uint32_t)pr[1]);
 }
@@ -84,15 +88,16 @@ __global__ __launch_bounds__(1024) void k_warp_dynamic(const int32_t *__restrict
       const auto add = [](uint32_t a, uint32_t b) { return a + b; };
       const auto mn = [](uint32_t a, uint32_t b) { return (int32_t)a < (int32_t)b ? a : b; };
       const auto mx = [](uint32_t a, uint32_t b) { return (int32_t)a > (int32_t)b ? a : b; };
-      const auto band = [](uint32_t a, uint32_t b) { return a & b; };
       const auto bor = [](uint32_t a, uint32_t b) { return a | b; };
       const auto bxor = [](uint32_t a, uint32_t b) { return a ^ b; };
-      const uint32_t ra = allreduce32(p ? ((uint32_t)xv & 0xFFFFu) : 0u, add);
-      const uint32_t rmn = allreduce32(p ? (uint32_t)xv : (uint32_t)INT32_MAX, mn);
-      const uint32_t rmx = allreduce32(p ? (uint32_t)xv : (uint32_t)INT32_MIN, mx);
-      const uint32_t rnd = allreduce32(p ? (uint32_t)xv : 0xFFFFFFFFu, band);
-      const uint32_t rr = allreduce32(p ? (uint32_t)xv : 0u, bor);
-      const uint32_t rx = allreduce32(p ? (uint32_t)xv : 0u, bxor);
+      const uint32_t ra = allreduce32<0u>(p ? ((uint32_t)xv & 0xFFFFu) : 0u, add);
+      const uint32_t rmn = allreduce32<(uint32_t)INT32_MAX>(p ? (uint32_t)xv : (uint32_t)INT32_MAX, mn);
+      const uint32_t rmx = allreduce32<(uint32_t)INT32_MIN>(p ? (uint32_t)xv : (uint32_t)INT32_MIN, mx);
+      // AND as the complement of the OR of the complements (an OR update
+      // folds into its op; an AND one does not)
+      const uint32_t rnd = ~allreduce32<0u>(p ? ~(uint32_t)xv : 0u, bor);
+      const uint32_t rr = allreduce32<0u>(p ? (uint32_t)xv : 0u, bor);
+      const uint32_t rx = allreduce32<0u>(p ? (uint32_t)xv : 0u, bxor);
       // match_any: m narrowed by one agreement ballot per key bit on which
       // the wave's members differ
       const uint32_t kvary = ((rr ^ rnd) >> 10) & 7u;
