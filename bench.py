@@ -199,7 +199,11 @@ def grid_sync_bench(iters=50, reps=3, rounds=2000):
     Algorithmic bytes per iteration: row_ptr 4 (n + 1) and the entries
     8 nnz, plus per row 16 bytes when the block's rows stay in registers
     (p and r gathered, p and r stored) or 40 bytes when they stream
-    through memory (also q stored, and p, q, x, r read, x stored)."""
+    through memory (also q stored, and p, q, x, r read, x stored).  When
+    the one-launch solve also keeps every block's CSR rows in shared memory
+    (they fit: at most 65535 entries and the compute unit's 160 KiB less
+    the static part), row_ptr and the entries are read once per solve and
+    count 1 / iters of their bytes per iteration."""
     import torch
 
     from paper_2112_10034_amd import cox, inputs
@@ -216,11 +220,16 @@ def grid_sync_bench(iters=50, reps=3, rounds=2000):
         d = [torch.from_numpy(a).cuda() for a in (rp, ci, val, b)]
         x = torch.zeros(n, dtype=torch.float32, device="cuda")
         nnz = ci.size
-        nch = -(-n // (32 * W * R))
+        S = 32 * W * R
+        nch = -(-n // S)
         resident = nch <= torch.cuda.get_device_properties(0).multi_processor_count
         row_bytes = 16 if resident else 40
+        # the resident kernel's fit rule, with its static shared memory
+        # (window of S + 128 floats, 2.3 KiB of reduction slots, 512 B slack)
+        most = int(max(rp[min((c + 1) * S, n)] - rp[c * S] for c in range(nch)))
+        staged = resident and most <= 0xFFFF and 4 * S + 8 * most <= 160 * 1024 - 4 * (S + 128) - 2368 - 512
         entry = {"rows": n, "nnz": int(nnz), "iterations": iters, "sigma": [R, W],
-                 "registers_resident": bool(resident)}
+                 "registers_resident": bool(resident), "csr_in_shared_memory": bool(staged)}
         for name, pp, rb in (("one_launch", False, row_bytes), ("per_phase", True, 40)):
             def solve():
                 x.zero_()
@@ -228,7 +237,8 @@ def grid_sync_bench(iters=50, reps=3, rounds=2000):
             ms = _timed(solve, reps)
             k = int(solve()[0][0].item())
             assert k == iters, (name, k)
-            nbytes = 4 * (n + 1) + 8 * nnz + rb * n
+            csr = 4 * (n + 1) + 8 * nnz
+            nbytes = (csr // iters if staged and not pp else csr) + rb * n
             us = ms * 1e3 / iters
             gbs = nbytes / (us * 1e-6) / 1e9
             entry[name] = {"us_per_iteration": round(us, 3), "algorithmic_bytes_per_iteration": int(nbytes),

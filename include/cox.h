@@ -439,7 +439,13 @@ cox_status cox_grid_exchange_absent(int32_t grid_blocks, int32_t rounds, int32_t
  *   tree per warp, then over the W warp values (-0.0 beyond W); the chunk
  *   values combined by the FP64 final tree of the reductions above.
  * Results depend on (items_per_lane, warps_per_block) only, never on the
- * grid.  cfg: items_per_lane 1, 2, 4 or 8, warps_per_block 8, 16 or 32
+ * grid, nor on where the kernel keeps its data.  With at most one chunk
+ * per block, x, r, p and q stay in registers for the whole solve, and a
+ * block whose rows fit in what shared memory the grid leaves (at most
+ * 65535 entries) reads its rows of row_ptr, col_idx and val once; if every
+ * such block's columns lie within 64 rows of its chunk, the blocks exchange
+ * only those halo rows of r and p through memory.
+ * cfg: items_per_lane 1, 2, 4 or 8, warps_per_block 8, 16 or 32
  * (COX_ERR_UNSUPPORTED otherwise), grid_blocks 0 = one block per compute
  * unit.  Malformed CSR (indices out of range) gives meaningless results
  * but no access outside the arrays.  n < 2^31 - 2^13, nnz < 2^31.

@@ -159,7 +159,7 @@ constexpr int HALO = 64;  // rows of the shared-memory window beyond the chunk o
 
 struct CgState {
   uint32_t stop;
-  uint32_t pad;
+  uint32_t far;  // resident kernel: some block gathers outside its window or streams its rows
   double rr[2];  // rr_k at slot k & 1 (per-phase launches)
 };
 
@@ -176,6 +176,7 @@ struct CgArgs {
   double *rr_hist;
   uint32_t *bar, *hdr;
   CgState *state;
+  uint32_t lds_bytes;  // dynamic shared memory of the resident kernel (0: CSR never staged)
 };
 
 // shared memory of one block
@@ -184,6 +185,7 @@ struct CgShared {
   double slot[32];
   double fin[256];
   double bcast;
+  uint32_t elo, ehi;  // entry range of the chunk's rows (CSR staging)
   float win[32 * W * R + 2 * HALO];
 };
 
@@ -392,6 +394,30 @@ __device__ __forceinline__ void cg_phase0_chunk(const CgArgs &a, int64_t c, SH &
   chunk_store<W>(s, a.prr, c, sh);
 }
 
+// rows of chunk c that other chunks' windows read: the first and last HALO
+__device__ __forceinline__ bool halo_row(int64_t c, int32_t row, int S) {
+  const int64_t o = (int64_t)row - c * S;
+  return o < HALO || o >= S - HALO;
+}
+
+// p of the chunk's rows from the window into p[k & 1], partials of <p, q>
+template <int R, int W, class SH>
+__device__ __forceinline__ void cg_phase1_tail(const CgArgs &a, int64_t c, const int32_t (&row)[R], int32_t w0,
+                                               float *pn, SH &sh, float (&pv)[R], const float (&qv)[R],
+                                               bool near = false) {
+  double s = -0.0;
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    pv[q] = 0.0f;
+    if (row[q] < a.n) {
+      pv[q] = sh.win[row[q] - w0];
+      if (!near || halo_row(c, row[q], 32 * W * R)) stcf(pn + row[q], pv[q]);
+      s = s + (double)pv[q] * (double)qv[q];
+    }
+  }
+  chunk_store<W>(s, a.ppq, c, sh);
+}
+
 // p (into p[k & 1]) and q = A p, partials of <p, q>
 template <int R, int W, int SU, class SH>
 __device__ __forceinline__ void cg_phase1_chunk(const CgArgs &a, int64_t c, int k, float beta, SH &sh, float (&pv)[R],
@@ -414,23 +440,135 @@ __device__ __forceinline__ void cg_phase1_chunk(const CgArgs &a, int64_t c, int 
     const float rj = ldcf(a.r + j);
     return first ? rj : __builtin_fmaf(beta, ldcf(pp + j), rj);
   });
-  double s = -0.0;
+  cg_phase1_tail<R, W>(a, c, row, w0, pn, sh, pv, qv);
+}
+
+// The resident kernel keeps its chunk's CSR rows in shared memory when they
+// fit in the launch's dynamic allocation: per row its clamped entry range
+// relative to the chunk's first entry (two 16-bit offsets), then the
+// (column, value) pairs with columns clamped as col_at does.  Decided per
+// block (uniformly); the staged values, and the order in which the SpMV
+// accumulates them, are those the streaming form reads.  Returns 0 (not
+// staged), 1 (staged; some column lies outside the chunk's window of
+// HALO rows on each side) or 2 (staged; every column inside the window).
+template <int R, int W, class SH>
+__device__ int cg_stage(const CgArgs &a, int64_t c, uint8_t *dyn, SH &sh) {
+  constexpr int BT = 32 * W, S = BT * R;
+  if (a.lds_bytes < (uint32_t)S * 4u) return 0;
+  int32_t row[R], lo[R], hi[R];
+  rows_of<R, W>(c, row);
+  if (threadIdx.x == 0) {
+    sh.elo = 0xffffffffu;
+    sh.ehi = 0u;
+  }
+  __syncthreads();
+  uint32_t mlo = 0xffffffffu, mhi = 0u;
 #pragma unroll
   for (int q = 0; q < R; q++) {
-    pv[q] = 0.0f;
+    lo[q] = hi[q] = 0;
     if (row[q] < a.n) {
-      pv[q] = sh.win[row[q] - w0];
-      stcf(pn + row[q], pv[q]);
-      s = s + (double)pv[q] * (double)qv[q];
+      row_bounds(a, row[q], lo[q], hi[q]);
+      mlo = min(mlo, (uint32_t)lo[q]);
+      mhi = max(mhi, (uint32_t)hi[q]);
     }
   }
-  chunk_store<W>(s, a.ppq, c, sh);
+  if (mlo != 0xffffffffu) {
+    atomicMin(&sh.elo, mlo);
+    atomicMax(&sh.ehi, mhi);
+  }
+  __syncthreads();
+  const uint32_t e0 = sh.elo, e1 = sh.ehi;
+  const uint32_t E = e1 > e0 ? e1 - e0 : 0u;
+  if (E > 0xffffu || (uint64_t)S * 4u + (uint64_t)E * 8u > a.lds_bytes) return 0;
+  uint32_t *bnd = (uint32_t *)dyn;
+  uint2 *ent = (uint2 *)(dyn + S * 4);
+#pragma unroll
+  for (int q = 0; q < R; q++)
+    bnd[BT * q + threadIdx.x] = row[q] < a.n ? ((uint32_t)lo[q] - e0) | (((uint32_t)hi[q] - e0) << 16) : 0u;
+  const int64_t cs = c * S;
+  const uint32_t w0 = (uint32_t)(cs > HALO ? cs - HALO : 0);
+  const uint32_t wn = (uint32_t)(cs + S + HALO < a.n ? cs + S + HALO : a.n) - w0;
+  int outside = 0;
+  for (uint32_t e = threadIdx.x; e < E; e += BT) {
+    const uint32_t j = col_at(a, (int32_t)(e0 + e));
+    outside |= j - w0 >= wn;
+    ent[e] = make_uint2(j, __float_as_uint(a.val[e0 + e]));
+  }
+  return __syncthreads_or(outside) ? 1 : 2;
+}
+
+// p over chunk c's window when no block reads outside its window: the
+// chunk's own rows from the registers (p_prev, r), the HALO rows on each
+// side from the neighbours' stores; ends with a block barrier
+template <int R, int W, class SH>
+__device__ __forceinline__ int32_t cg_window_near(const CgArgs &a, int64_t c, bool first, float beta, const float *pp,
+                                                  const float (&pv)[R], const float (&rv)[R], SH &sh, int32_t &wn) {
+  constexpr int BT = 32 * W, S = BT * R;
+  const int64_t lo = c * S;
+  const int32_t w0 = (int32_t)(lo > HALO ? lo - HALO : 0);
+  const int32_t w1 = (int32_t)(lo + S + HALO < a.n ? lo + S + HALO : a.n);
+  const int t = threadIdx.x;
+  if (t < 2 * HALO) {
+    const int32_t j = t < HALO ? (int32_t)lo - HALO + t : (int32_t)(lo + S) + (t - HALO);
+    if (j >= w0 && j < w1) {
+      const float rj = ldcf(a.r + j);
+      sh.win[j - w0] = first ? rj : __builtin_fmaf(beta, ldcf(pp + j), rj);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    const int32_t j = (int32_t)lo + BT * q + t;
+    if (j < a.n) sh.win[j - w0] = first ? rv[q] : __builtin_fmaf(beta, pv[q], rv[q]);
+  }
+  __syncthreads();
+  wn = w1 - w0;
+  return w0;
+}
+
+// phase 1 of the resident kernel on staged rows; near: no block reads
+// outside its window, so the window comes from registers and halos and
+// only the halo rows of p are stored
+template <int R, int W, class SH>
+__device__ __forceinline__ void cg_phase1_chunk_lds(const CgArgs &a, int64_t c, int k, float beta, SH &sh,
+                                                    const uint8_t *dyn, bool near, float (&pv)[R], float (&qv)[R],
+                                                    const float (&rv)[R]) {
+  constexpr int BT = 32 * W, S = BT * R;
+  const bool first = k == 0;
+  const float *pp = a.p[(k + 1) & 1];
+  float *pn = a.p[k & 1];
+  int32_t row[R];
+  rows_of<R, W>(c, row);
+  int32_t wn;
+  const int32_t w0 = near ? cg_window_near<R, W>(a, c, first, beta, pp, pv, rv, sh, wn)
+                          : cg_window<R, W>(a, c, first, beta, pp, sh, wn);
+  const uint32_t *bnd = (const uint32_t *)dyn;
+  const uint2 *ent = (const uint2 *)(dyn + S * 4);
+#pragma unroll
+  for (int q = 0; q < R; q++) {
+    const uint32_t bq = bnd[BT * q + threadIdx.x];
+    float acc = 0.0f;
+    for (uint32_t e = bq & 0xffffu; e < (bq >> 16); e++) {
+      const uint2 ev = ent[e];
+      const uint32_t o = ev.x - (uint32_t)w0;
+      float g;
+      if (o < (uint32_t)wn) {
+        g = sh.win[o];
+      } else {
+        const float rj = ldcf(a.r + ev.x);
+        g = first ? rj : __builtin_fmaf(beta, ldcf(pp + ev.x), rj);
+      }
+      acc = __builtin_fmaf(__uint_as_float(ev.y), g, acc);
+    }
+    qv[q] = acc;
+  }
+  cg_phase1_tail<R, W>(a, c, row, w0, pn, sh, pv, qv, near);
 }
 
 // x = fmaf(alpha, p, x), r = fmaf(-alpha, q, r), partials of <r, r>
 template <int R, int W, class SH>
 __device__ __forceinline__ void cg_phase2_chunk(const CgArgs &a, int64_t c, float alpha, SH &sh, const float (&pv)[R],
-                                                const float (&qv)[R], float (&xv)[R], float (&rv)[R]) {
+                                                const float (&qv)[R], float (&xv)[R], float (&rv)[R],
+                                                bool near = false) {
   int32_t row[R];
   rows_of<R, W>(c, row);
   double s = -0.0;
@@ -439,7 +577,7 @@ __device__ __forceinline__ void cg_phase2_chunk(const CgArgs &a, int64_t c, floa
     if (row[q] < a.n) {
       xv[q] = __builtin_fmaf(alpha, pv[q], xv[q]);
       rv[q] = __builtin_fmaf(-alpha, qv[q], rv[q]);
-      stcf(a.r + row[q], rv[q]);
+      if (!near || halo_row(c, row[q], 32 * W * R)) stcf(a.r + row[q], rv[q]);
       s = s + (double)rv[q] * (double)rv[q];
     }
   }
@@ -534,16 +672,25 @@ __global__ __launch_bounds__(32 * W) void k_cg(CgArgs a) {
 }
 
 // the same solve with at most one chunk per block (gridDim.x >= nch): the
-// block's x, r, p and q stay in registers; x is stored once at the end
+// block's x, r, p and q stay in registers, its CSR rows in shared memory
+// when they fit; x is stored once at the end
 template <int R, int W>
 __global__ __launch_bounds__(32 * W) void k_cg_res(CgArgs a) {
   __shared__ CgShared<R, W> sh;
+  extern __shared__ __align__(16) uint8_t cg_dyn[];
   const int64_t c = blockIdx.x;
   const bool own = c < a.nch;  // uniform over the block
   float xv[R], rv[R], pv[R], qv[R];
   int32_t k = 0, reason = CG_ABORTED;
+  const int stage = own ? cg_stage<R, W>(a, c, cg_dyn, sh) : 2;  // uniform over the block
+  const bool staged = own && stage > 0;
+  // a block that streams its rows or gathers outside its window needs
+  // every row of r and p in memory
+  if (stage < 2 && threadIdx.x == 0) __hip_atomic_fetch_or(&a.state->far, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (own) cg_phase0_chunk<R, W, su_resident<R>()>(a, c, sh, xv, rv);
   if (grid_sync(a.bar, a.hdr)) {
+    // the same word for every thread, written before the barrier
+    const bool near = staged && ldc32(&a.state->far) == 0u;
     double rr = final64(a.prr, a.nch, sh), rr_prev = 0.0;
     for (;; k++) {
       if (lead() && a.rr_hist) a.rr_hist[k] = rr;
@@ -555,14 +702,18 @@ __global__ __launch_bounds__(32 * W) void k_cg_res(CgArgs a) {
         reason = CG_MAX_ITER;
         break;
       }
-      if (own) cg_phase1_chunk<R, W, su_resident<R>()>(a, c, k, k ? (float)(rr / rr_prev) : 0.0f, sh, pv, qv);
+      const float beta = k ? (float)(rr / rr_prev) : 0.0f;
+      if (staged)
+        cg_phase1_chunk_lds<R, W>(a, c, k, beta, sh, cg_dyn, near, pv, qv, rv);
+      else if (own)
+        cg_phase1_chunk<R, W, su_resident<R>()>(a, c, k, beta, sh, pv, qv);
       if (!grid_sync(a.bar, a.hdr)) break;
       const double pq = final64(a.ppq, a.nch, sh);
       if (!(pq > 0.0)) {
         reason = CG_BREAKDOWN;
         break;
       }
-      if (own) cg_phase2_chunk<R, W>(a, c, (float)(rr / pq), sh, pv, qv, xv, rv);
+      if (own) cg_phase2_chunk<R, W>(a, c, (float)(rr / pq), sh, pv, qv, xv, rv, near);
       if (!grid_sync(a.bar, a.hdr)) break;
       rr_prev = rr;
       rr = final64(a.prr, a.nch, sh);
@@ -737,14 +888,32 @@ static cox_status cg_run(const int32_t *row_ptr, const int32_t *col_idx, const f
   a.bar = (uint32_t *)(w + L.bar);
   a.hdr = (uint32_t *)w;
   a.state = (CgState *)(w + L.state);
+  a.lds_bytes = 0;
   hipStream_t hs = (hipStream_t)stream;
+  const void *fn = G >= nch ? pk.coop_res : pk.coop;
+  if (coop && G >= nch) {
+    // the resident kernel stages CSR rows in what shared memory the grid
+    // leaves: the compute unit's share per block less the static part
+    hipFuncAttributes fa;
+    const int cus = device_cus(), per_cu = (G + cus - 1) / cus;
+    if (hipFuncGetAttributes(&fa, fn) == hipSuccess) {
+      const size_t share = device_max_lds() / (size_t)per_cu, fixed = fa.sharedSizeBytes + 512;
+      const size_t dyn = share > fixed ? (share - fixed) & ~(size_t)15 : 0;
+      if (dyn >= (size_t)S * 4 + 1024 &&
+          (dyn <= 65536 ||
+           hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) == hipSuccess) &&
+          (int64_t)blocks_per_cu(fn, block, dyn) * cus >= G)
+        a.lds_bytes = (uint32_t)dyn;
+    }
+    (void)hipGetLastError();  // a refused attribute only means no staging
+  }
   // barrier words and solver state start at zero on every call
   hipLaunchKernelGGL(k_grid_clear, dim3(1), dim3(256), 0, hs, a.bar, (int)((GB_BYTES + 256) / 4));
   if ((st = launch_status()) != COX_OK) return st;
   if (coop) {
     // one chunk per block at most: the register-resident kernel
     void *args[] = {&a};
-    const hipError_t e = hipLaunchCooperativeKernel(G >= nch ? pk.coop_res : pk.coop, dim3(G), dim3(block), args, 0, hs);
+    const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(block), args, a.lds_bytes, hs);
     if (e != hipSuccess) {
       set_hip_error(e);
       return COX_ERR_HIP;

@@ -7,7 +7,8 @@
    iteration count, the stop reason and every rr_k bit-exact against the
    oracle on the same inner-product schedule, for sizes that span one
    chunk, several chunks with a ragged tail, and the full workload sizes;
-   results identical for every grid size.
+   results identical for every grid size, and whether a block of the
+   resident kernel keeps its CSR rows in shared memory or streams them.
 """
 import numpy as np
 import pytest
@@ -120,15 +121,54 @@ def test_cg_matches_oracle(dev, oracle_mod, kind, n, sigma, max_iter, tol, per_p
         assert want[2] == oracle_mod.CG_CONVERGED
 
 
+@pytest.mark.parametrize("kind", ["irr", "tri"])
 @pytest.mark.parametrize("grid", [1, 3, 7, 0])
-def test_cg_result_is_independent_of_the_grid(dev, oracle_mod, grid):
+def test_cg_result_is_independent_of_the_grid(dev, oracle_mod, grid, kind):
+    """Grids below the chunk count run the streaming kernel, the others the
+    resident one; the tridiagonal rows fit in shared memory there, the
+    irregular ones (seven entries a row) do not."""
     torch, cox = dev
     n = 5 * 4096 + 99
-    sysm = _system("irr", n, seed=4)
+    sysm = _system(kind, n, seed=4)
     x0 = np.linspace(-1, 1, n).astype(np.float32)
-    print("cg grid", grid, flush=True)
+    print("cg grid", kind, grid, flush=True)
     want = oracle_mod.cg(*sysm, x0, 20, 0.0, 4, 32)
     _check(_solve(torch, cox, sysm, x0, 20, 0.0, (4, 32), False, grid), want)
+
+
+def _block_diagonal(S, tail, seed):
+    """SPD block-diagonal system: a tridiagonal block over the first two
+    chunks of S rows, then a band of half-width 8 (17 entries a row) over
+    S + tail rows.  In the resident kernel the first two chunks and the
+    short last chunk keep their rows in shared memory, the third (about
+    17 S entries) cannot."""
+    sp = pytest.importorskip("scipy.sparse")
+    rng = np.random.default_rng(seed)
+    n1, n2 = 2 * S, S + tail
+    off1 = -rng.random(n1 - 1)
+    T = sp.diags([off1, 3.0 + rng.random(n1), off1], [-1, 0, 1])
+    bands = [20.0 + rng.random(n2)]
+    offs = [0]
+    for d in range(1, 9):
+        v = -rng.random(n2 - d)
+        bands += [v, v]
+        offs += [d, -d]
+    B = sp.diags(bands, offs)
+    A = sp.block_diag((T, B)).astype(np.float32).tocsr()
+    A.sort_indices()
+    b = rng.uniform(-1, 1, n1 + n2).astype(np.float32)
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float32), b
+
+
+def test_cg_with_staged_and_streamed_blocks(dev, oracle_mod):
+    torch, cox = dev
+    sysm = _block_diagonal(4096, 17, seed=11)
+    n = sysm[3].size
+    x0 = np.zeros(n, np.float32)
+    print("cg staged and streamed blocks", n, flush=True)
+    want = oracle_mod.cg(*sysm, x0, 30, 0.0, 4, 32)
+    for pp in (False, True):
+        _check(_solve(torch, cox, sysm, x0, 30, 0.0, (4, 32), pp), want)
 
 
 def test_cg_degenerate_cases(dev, oracle_mod):
