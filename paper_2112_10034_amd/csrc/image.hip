@@ -6,10 +6,11 @@
 // per pixel: 1 + 4 read, 4 + 4 written), the image is cut into tiles of
 // TH rows x TW columns (band b, segment s) and reduced, carried, then
 // scanned:
-//   k_ii_reduce  per tile: column sums (colsum[b][x]), row sums
+//   k_ii_reduce  per tile (k_ii_reduce16 with 16-pixel loads where the
+//                shape allows): column sums (colsum[b][x]), row sums
 //                (rowsum[s][y]) and the tile total (total[b][s]);
 //   k_ii_colscan per column: colsum[b][x] replaced by its exclusive prefix
-//                over the bands above, T[b][x];
+//                over the bands above, T[b][x] (8 waves per 64 columns);
 //   k_ii_scan    per tile: sat[y][x] = rowprefix_x(T[b][.] + column sums
 //                of rows y0..y)[x] + corner + sum of L over rows y0..y,
 //                with L[y] the row sums of the segments to the left and
@@ -149,20 +150,143 @@ __global__ __launch_bounds__(II_BT) void k_ii_reduce(IiArgs a) {
   }
 }
 
-// exclusive prefix of every column's band sums, 64 bands per batch of loads
-__global__ __launch_bounds__(256) void k_ii_colscan(IiArgs a) {
-  constexpr int NB = 64;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < a.W; x += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t run = 0u;
-    for (int64_t b0 = 0; b0 < a.nb; b0 += NB) {
-      uint32_t v[NB];
+// value of lane t ^ 32 of the wave: every lane receives the other half's
+// value of the same register
+__device__ __forceinline__ uint32_t ii_xor32(uint32_t v) {
+  const auto pr = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+  return lhalf() ? (uint32_t)pr[0] : (uint32_t)pr[1];
+}
+
+// Sums of 16 values over the 64 lanes of a wave: a butterfly that halves
+// the values a lane holds at every step (xor 32, 16, 8, 4), then two plain
+// steps (xor 2, 1).  Returns, in every lane, the wave sum of value
+// ((lane >> 2) & 15).
+__device__ __forceinline__ uint32_t ii_wave_sum16(const uint32_t (&v)[16]) {
+  const int L = (int)__lane_id();
+  uint32_t a[8], b[4], c[2];
+  const bool h32 = (L & 32) != 0, h16 = (L & 16) != 0, h8 = (L & 8) != 0, h4 = (L & 4) != 0;
 #pragma unroll
-      for (int k = 0; k < NB; k++) v[k] = b0 + k < a.nb ? a.colsum[(b0 + k) * a.W + x] : 0u;
+  for (int i = 0; i < 8; i++) a[i] = (h32 ? v[i + 8] : v[i]) + ii_xor32(h32 ? v[i] : v[i + 8]);
 #pragma unroll
-      for (int k = 0; k < NB; k++) {
-        if (b0 + k < a.nb) a.colsum[(b0 + k) * a.W + x] = run;
-        run += v[k];
+  for (int i = 0; i < 4; i++) b[i] = (h16 ? a[i + 4] : a[i]) + (uint32_t)xor_lane<16>((int)(h16 ? a[i] : a[i + 4]));
+#pragma unroll
+  for (int i = 0; i < 2; i++) c[i] = (h8 ? b[i + 2] : b[i]) + (uint32_t)xor_lane<8>((int)(h8 ? b[i] : b[i + 2]));
+  uint32_t d = (h4 ? c[1] : c[0]) + (uint32_t)xor_lane<4>((int)(h4 ? c[0] : c[1]));
+  d += (uint32_t)xor_lane<2>((int)d);
+  d += (uint32_t)xor_lane<1>((int)d);
+  return d;
+}
+
+// Tile sums with 16-pixel loads (width a multiple of 16, image 16-byte
+// aligned).  Lane c of wave g covers columns 16c .. 16c + 15 of the tile
+// and rows g, g + 4, .., g + 60, so a row's sum is a wave sum; the four
+// waves' column sums meet in shared memory.  Same outputs as k_ii_reduce.
+__global__ __launch_bounds__(II_BT) void k_ii_reduce16(IiArgs a) {
+  static_assert(II_BT == 256 && II_TW == 1024 && II_TH == 64, "4 waves x 64 lanes x 16 columns, 16 rows a wave");
+  __shared__ __align__(16) uint32_t s_col[4][II_TW];
+  __shared__ uint32_t s_tot[4];
+  const int t = threadIdx.x, g = t >> 6, L = t & 63;
+  for (int64_t tile = blockIdx.x; tile < a.nb * a.ns; tile += gridDim.x) {
+    const int64_t b = tile / a.ns, s = tile % a.ns;
+    const int64_t y0 = b * II_TH, x = s * II_TW + 16 * L;
+    const int rows = (int)(a.H - y0 < II_TH ? a.H - y0 : II_TH);
+    const bool okx = x < a.W;
+    // column sums packed two to a word (even and odd bytes in 16-bit
+    // halves; at most 16 * 255 each, no carry between halves), row sums by
+    // v_sad_u8 against zero; rows in two batches of 8 loads
+    uint32_t ev[4] = {0u, 0u, 0u, 0u}, od[4] = {0u, 0u, 0u, 0u}, rs[16];
+#pragma unroll
+    for (int i0 = 0; i0 < 16; i0 += 8) {
+      u32x4 px[8];
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        const int r = g + 4 * (i0 + i);
+        px[i] = okx && r < rows ? ld_stream4(a.img + (y0 + r) * a.W + x) : u32x4{0u, 0u, 0u, 0u};
       }
+#pragma unroll
+      for (int i = 0; i < 8; i++) {
+        uint32_t sum = 0u;
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+          const uint32_t word = px[i][w];
+          ev[w] += word & 0x00ff00ffu;
+          od[w] += (word >> 8) & 0x00ff00ffu;
+          sum = __builtin_amdgcn_sad_u8(word, 0u, sum);
+        }
+        rs[i0 + i] = sum;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    uint32_t cs[16];
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+      cs[4 * w + 0] = ev[w] & 0xffffu;
+      cs[4 * w + 1] = od[w] & 0xffffu;
+      cs[4 * w + 2] = ev[w] >> 16;
+      cs[4 * w + 3] = od[w] >> 16;
+    }
+    // row g + 4 * slot of the tile, slot = (lane >> 2) & 15
+    const uint32_t row_sum = ii_wave_sum16(rs);
+    const int r = g + 4 * ((L >> 2) & 15);
+    if ((L & 3) == 0 && r < rows) a.rowsum[s * a.H + y0 + r] = row_sum;
+    // tile total: every row sum once (lanes with (L & 3) == 0), per wave
+    uint32_t tv = (L & 3) == 0 && r < rows ? row_sum : 0u;
+    tv = ii_warp_sum(tv);
+    tv += ii_xor32(tv);
+    if (L == 0) s_tot[g] = tv;
+#pragma unroll
+    for (int j = 0; j < 16; j += 4)
+      *(u32x4 *)&s_col[g][16 * L + j] = u32x4{cs[j], cs[j + 1], cs[j + 2], cs[j + 3]};
+    __syncthreads();
+    {
+      const int c0 = 4 * t;  // 4 columns a thread
+      const int64_t xc = s * II_TW + c0;
+      uint32_t out[4];
+#pragma unroll
+      for (int j = 0; j < 4; j++) out[j] = s_col[0][c0 + j] + s_col[1][c0 + j] + s_col[2][c0 + j] + s_col[3][c0 + j];
+      if (xc < a.W) *(u32x4 *)&a.colsum[b * a.W + xc] = u32x4{out[0], out[1], out[2], out[3]};
+    }
+    if (t == 0) a.total[b * a.ns + s] = s_tot[0] + s_tot[1] + s_tot[2] + s_tot[3];
+    __syncthreads();
+  }
+}
+
+// exclusive prefix of every column's band sums.  A block takes 64
+// columns (one per lane) and batches of 8 x 16 bands: wave g loads and
+// sums bands g*16 .. g*16 + 15 of the batch, the 8 group sums meet in
+// shared memory, and every wave writes its bands' exclusive prefixes
+// (carry of the batches above + groups above + its own bands above).
+constexpr int II_CS_WAVES = 8, II_CS_PB = 16;
+__global__ __launch_bounds__(64 * II_CS_WAVES) void k_ii_colscan(IiArgs a) {
+  __shared__ uint32_t s_grp[II_CS_WAVES][64];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  for (int64_t x0 = (int64_t)blockIdx.x * 64; x0 < a.W; x0 += (int64_t)gridDim.x * 64) {
+    const int64_t x = x0 + lane;
+    const bool okx = x < a.W;
+    uint32_t carry = 0u;
+    for (int64_t b0 = 0; b0 < a.nb; b0 += II_CS_WAVES * II_CS_PB) {
+      const int64_t bg = b0 + (int64_t)g * II_CS_PB;
+      uint32_t v[II_CS_PB], sum = 0u;
+#pragma unroll
+      for (int k = 0; k < II_CS_PB; k++) v[k] = okx && bg + k < a.nb ? a.colsum[(bg + k) * a.W + x] : 0u;
+#pragma unroll
+      for (int k = 0; k < II_CS_PB; k++) sum += v[k];
+      s_grp[g][lane] = sum;
+      __syncthreads();
+      uint32_t off = carry, tot = 0u;
+#pragma unroll
+      for (int h = 0; h < II_CS_WAVES; h++) {
+        const uint32_t u = s_grp[h][lane];
+        off += h < g ? u : 0u;
+        tot += u;
+      }
+#pragma unroll
+      for (int k = 0; k < II_CS_PB; k++) {
+        if (okx && bg + k < a.nb) a.colsum[(bg + k) * a.W + x] = off;
+        off += v[k];
+      }
+      carry += tot;
+      __syncthreads();  // s_grp is rewritten by the next batch
     }
   }
 }
@@ -296,14 +420,15 @@ extern "C" cox_status cox_integral_image(const uint8_t *img, int64_t height, int
   a.rowsum = (uint32_t *)(w + L.rowsum);
   a.total = (uint32_t *)(w + L.total);
   const bool vec = width % 4 == 0 && ((uintptr_t)img & 3u) == 0 && aligned16(sat);
-  auto reduce = vec ? k_ii_reduce<true> : k_ii_reduce<false>;
+  const bool vec16 = width % 16 == 0 && ((uintptr_t)img & 15u) == 0;
+  auto reduce = vec16 ? k_ii_reduce16 : vec ? k_ii_reduce<true> : k_ii_reduce<false>;
   auto scan = vec ? k_ii_scan<true> : k_ii_scan<false>;
   hipStream_t hs = (hipStream_t)stream;
   const int64_t tiles = a.nb * a.ns;
   const int g1 = persistent_grid((const void *)reduce, II_BT, tiles, 0, 0, 8);
   hipLaunchKernelGGL(reduce, dim3(g1), dim3(II_BT), 0, hs, a);
-  const int64_t gc = (width + 255) / 256;
-  hipLaunchKernelGGL(k_ii_colscan, dim3((unsigned)(gc < 65536 ? gc : 65536)), dim3(256), 0, hs, a);
+  const int64_t gc = (width + 63) / 64;
+  hipLaunchKernelGGL(k_ii_colscan, dim3((unsigned)(gc < 65536 ? gc : 65536)), dim3(64 * II_CS_WAVES), 0, hs, a);
   const int g3 = persistent_grid((const void *)scan, II_BT, tiles, 0, 0, 8);
   hipLaunchKernelGGL(scan, dim3(g3), dim3(II_BT), 0, hs, a);
   return launch_status();

@@ -21,8 +21,12 @@ def dev():
     return torch, cox
 
 
+# widths that are multiples of 16 take the 16-pixel tile-sum kernel: (3, 2048)
+# has fewer rows than its waves, (17, 16) one 16-column group, (8320, 80)
+# more than 128 bands (the column pass carries across its batches)
 @pytest.mark.parametrize("H,W", [(1, 1), (1, 777), (555, 1), (64, 1024), (65, 1025), (99, 1999), (300, 4099),
-                                 (1080, 1920), (2000, 3000), (1999, 3001), (4200, 4200)])
+                                 (1080, 1920), (2000, 3000), (1999, 3001), (4200, 4200), (3, 2048), (17, 16),
+                                 (8320, 80), (4200, 4096)])
 def test_integral_image_matches_oracle(dev, oracle_mod, H, W):
     torch, cox = dev
     img = inputs.image_u8(H, W, seed=H + 13 * W)
