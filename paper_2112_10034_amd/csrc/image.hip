@@ -363,7 +363,9 @@ __global__ __launch_bounds__(II_BT) void k_ii_scan(IiArgs a) {
         const int64_t y = y0 + r0 + r;
         uint32_t *dst = a.sat + y * a.W + x;
         if constexpr (VEC) {
-          if (x < a.W) st_stream4(dst, q[r][0] + off, q[r][1] + off, q[r][2] + off, q[r][3] + off);
+          // plain (cached) stores: the table is four times the image, and
+          // for write-dominated traffic they beat non-temporal stores
+          if (x < a.W) *(u32x4 *)dst = u32x4{q[r][0] + off, q[r][1] + off, q[r][2] + off, q[r][3] + off};
         } else {
 #pragma unroll
           for (int j = 0; j < 4; j++)
