@@ -279,16 +279,46 @@ def test_masked_ops_definition(oracle_mod, D):
 
 
 # ---------------------------------------------------------------- FP trees
-def _sigma_tree_np(x, k, W, compensated=False):
+def _fmaf_np(a, b, c):
+    """Correctly rounded binary32 fused multiply-add, from its definition:
+    the product of two binary32 values is exact in binary64; (p + c) is
+    formed as s + e exactly (TwoSum in binary64); s is rounded to binary32,
+    except where s lies exactly halfway between two binary32 values and
+    e != 0, where the exact value is on e's side of the midpoint (s is
+    first moved one binary64 ulp towards it)."""
+    a, b, c = (np.asarray(v, np.float32).astype(np.float64) for v in (a, b, c))
+    p = a * b
+    s = p + c
+    bb = s - p
+    e = (p - (s - bb)) + (c - bb)
+    t = s.astype(np.float32)
+    tt = t.astype(np.float64)
+    lo = np.where(tt > s, np.nextafter(t, np.float32(-np.inf)), t).astype(np.float64)
+    hi = np.where(tt > s, t, np.nextafter(t, np.float32(np.inf))).astype(np.float64)
+    tie = (s == (lo + hi) / 2) & (e != 0) & (tt != s)
+    s2 = np.where(tie, np.nextafter(s, np.where(e > 0, np.inf, -np.inf)), s)
+    return s2.astype(np.float32)
+
+
+def _sigma_tree_np(x, k, W, compensated=False, y=None, V=4):
     """Independent array-halving form of the fixed reduction schedule:
     lane-serial accumulation in (row, vector-slot) order, then the shfl_down
-    tree at lane 0 written as recursive halving (lanes l and l + h)."""
-    T, V = 32 * W, min(k, 4)
+    tree at lane 0 written as recursive halving (lanes l and l + h).
+    x (and y for a dot) are binary32 values (bfloat16 inputs widened
+    exactly); V is the vector width of the element mapping (4 for 4-byte
+    elements, 8 for bfloat16), capped at k.  Sum: s + x, or TwoSum
+    compensation; dot: s = fmaf(x, y, s), or Dot2 (TwoProduct, TwoSum,
+    c = c + (pe + q)); tails pad x with -0.0 and y with +0.0."""
+    T, V = 32 * W, min(k, V)
     R, S = k // V, 32 * W * k
     nch = -(-x.size // S)
     xp = np.full(nch * S, -0.0, np.float32)
     xp[: x.size] = x
     a = xp.reshape(nch, W, R, 32, V)
+    if y is not None:
+        yp = np.zeros(nch * S, np.float32)
+        yp[: y.size] = y
+        b = yp.reshape(nch, W, R, 32, V)
     s = np.full((nch, W, 32), -0.0, np.float32)
     c = np.full((nch, W, 32), -0.0, np.float32)
 
@@ -299,11 +329,22 @@ def _sigma_tree_np(x, k, W, compensated=False):
 
     for i in range(R):
         for v in range(V):
-            if compensated:
-                s, e = two_sum(s, a[:, :, i, :, v])
-                c = c + e
+            xv = a[:, :, i, :, v]
+            if y is None:
+                if compensated:
+                    s, e = two_sum(s, xv)
+                    c = c + e
+                else:
+                    s = s + xv
             else:
-                s = s + a[:, :, i, :, v]
+                yv = b[:, :, i, :, v]
+                if compensated:
+                    p = xv * yv
+                    pe = (xv.astype(np.float64) * yv.astype(np.float64) - p.astype(np.float64)).astype(np.float32)
+                    s, q = two_sum(s, p)
+                    c = c + (pe + q)
+                else:
+                    s = _fmaf_np(xv, yv, s)
 
     def halve(s, c):
         while s.shape[-1] > 1:
@@ -362,6 +403,148 @@ def test_fp32_twosum_tree_matches_halving_form(oracle_mod, k, W):
     assert np.array_equal(part[:, 1].view(np.uint32), wc.view(np.uint32))
     vals = part[:, 0].astype(np.float64) + part[:, 1].astype(np.float64)
     assert np.float64(tot) == _final_np(vals)
+
+
+def test_fmaf_np_is_the_correctly_rounded_fma():
+    """The halving form's FMA against exact rational arithmetic, rounded
+    to binary32 by hand (nearest, ties to even), on random operands and on
+    constructed ties where rounding p + c in binary64 first would be wrong."""
+    r = rng(11)
+    a = (r.standard_normal(3000) * 10.0 ** r.uniform(-3, 3, 3000)).astype(np.float32)
+    b = (r.standard_normal(3000) * 10.0 ** r.uniform(-3, 3, 3000)).astype(np.float32)
+    c = (r.standard_normal(3000) * 10.0 ** r.uniform(-6, 6, 3000)).astype(np.float32)
+    # ties: a*b = 1 + 2^-24 + 2^-47 (just above a binary32 midpoint), c = 0,
+    # and products whose low part decides the direction next to a midpoint
+    a = np.concatenate([a, np.float32([1 + 2.0 ** -23, 1 + 2.0 ** -12, 3.0])])
+    b = np.concatenate([b, np.float32([1 + 2.0 ** -23, 1 + 2.0 ** -12 - 2.0 ** -23, 1 + 2.0 ** -22])])
+    c = np.concatenate([c, np.float32([-1.0, 2.0 ** -30, -2.0 ** -40])])
+    got = _fmaf_np(a, b, c)
+
+    def rn32(q):
+        if q == 0:
+            return 0.0
+        m, ex = math.frexp(float(q))  # only for the scale; the rounding below is exact
+        e = ex - 24
+        while Fraction(2) ** (e + 24) <= abs(q):
+            e += 1
+        while Fraction(2) ** (e + 23) > abs(q):
+            e -= 1
+        unit = Fraction(2) ** e
+        t = q / unit
+        fl = math.floor(t)
+        rem = t - fl
+        if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+            fl += 1
+        return float(fl * unit)
+
+    for x, yv, z, g in zip(a.tolist(), b.tolist(), c.tolist(), got.tolist()):
+        want = rn32(Fraction(x) * Fraction(yv) + Fraction(z))
+        assert np.float32(want).view(np.uint32) == np.float32(g).view(np.uint32) or (want == 0 and g == 0), (x, yv, z)
+
+
+def _bf16_case(n, seed):
+    r = rng(seed)
+    bits = inputs._to_bf16_bits((r.standard_normal(n) * 10.0 ** r.uniform(-2, 2, n)).astype(np.float32))
+    return bits, inputs.bf16_to_f32(bits)
+
+
+@pytest.mark.parametrize("k,W", SIGMAS)
+@pytest.mark.parametrize("acc", [0, 1])
+def test_bf16_reduce_tree_matches_halving_form(oracle_mod, k, W, acc):
+    """bfloat16 inputs: eight elements per 16-byte vector (V = min(k, 8))."""
+    bits, f = _bf16_case(40_000 + 5, 12)
+    part, tot = oracle_mod.reduce(bits, k, W, acc)
+    ws, wc = _sigma_tree_np(f, k, W, compensated=bool(acc), V=8)
+    if acc:
+        assert np.array_equal(part[:, 0].view(np.uint32), ws.view(np.uint32))
+        assert np.array_equal(part[:, 1].view(np.uint32), wc.view(np.uint32))
+        vals = part[:, 0].astype(np.float64) + part[:, 1].astype(np.float64)
+    else:
+        assert np.array_equal(part.view(np.uint32), ws.view(np.uint32))
+        vals = part.astype(np.float64)
+    assert np.float64(tot).view(np.uint64) == np.float64(_final_np(vals)).view(np.uint64)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+@pytest.mark.parametrize("k,W", SIGMAS)
+@pytest.mark.parametrize("acc", [0, 1])
+def test_dot_tree_matches_halving_form(oracle_mod, dtype, k, W, acc):
+    """Plain dot: s = fmaf(x, y, s) per element (one rounding, not two);
+    Dot2: TwoProduct by the exact binary64 product, TwoSum, and the
+    correction c + (pe + q).  Tails pad x with -0.0 and y with +0.0."""
+    n = 30_000 + 7
+    if dtype == "f32":
+        r = rng(13)
+        x = (r.standard_normal(n) * 10.0 ** r.uniform(-2, 2, n)).astype(np.float32)
+        y = (r.standard_normal(n) * 10.0 ** r.uniform(-2, 2, n)).astype(np.float32)
+        xa, ya, V = x, y, 4
+    else:
+        xa, x = _bf16_case(n, 14)
+        ya, y = _bf16_case(n, 15)
+        V = 8
+    part, tot = oracle_mod.dot(xa, ya, k, W, acc)
+    ws, wc = _sigma_tree_np(x, k, W, compensated=bool(acc), y=y, V=V)
+    if acc:
+        assert np.array_equal(part[:, 0].view(np.uint32), ws.view(np.uint32))
+        assert np.array_equal(part[:, 1].view(np.uint32), wc.view(np.uint32))
+        vals = part[:, 0].astype(np.float64) + part[:, 1].astype(np.float64)
+    else:
+        assert np.array_equal(part.view(np.uint32), ws.view(np.uint32))
+        vals = part.astype(np.float64)
+    assert np.float64(tot).view(np.uint64) == np.float64(_final_np(vals)).view(np.uint64)
+
+
+@pytest.mark.parametrize("acc", [0, 1])
+def test_signed_zero_dot_and_sum(oracle_mod, acc):
+    """-0.0 times +1.0 is -0.0 and a sum of -0.0 is -0.0 in round to
+    nearest, so every plain partial and total is -0.0 -- including the
+    ragged last chunk, whose padding (x = -0.0, y = +0.0) must leave a
+    -0.0 accumulator unchanged.  Compensated: the sums s stay -0.0, and
+    TwoSum's error of (-0.0) + (-0.0) is (-0.0 - (-0.0)) + (-0.0 - (+0.0))
+    = +0.0, so every compensation c and the total s + c are +0.0."""
+    n = 32 * 8 * 4 * 3 + 77
+    x = np.full(n, -0.0, np.float32)
+    y = np.ones(n, np.float32)
+    want_tot = np.float64(-0.0 if acc == 0 else 0.0).view(np.uint64)
+
+    def check(part):
+        if acc == 0:
+            assert np.all(part.view(np.uint32) == 0x80000000)
+        else:
+            assert np.all(part[:, 0].view(np.uint32) == 0x80000000)
+            assert np.all(part[:, 1].view(np.uint32) == 0)
+
+    for k, W in ((4, 8), (1, 1), (8, 2)):
+        part, tot = oracle_mod.dot(x, y, k, W, acc)
+        check(part)
+        assert np.float64(tot).view(np.uint64) == want_tot, (k, W)
+        part, tot = oracle_mod.reduce(x, k, W, acc)
+        check(part)
+        assert np.float64(tot).view(np.uint64) == want_tot, (k, W)
+    bits = np.full(n, 0x8000, np.uint16)  # bfloat16 -0.0 times +1.0
+    part, tot = oracle_mod.dot(bits, np.full(n, 0x3F80, np.uint16), 16, 8, acc)
+    check(part)
+    assert np.float64(tot).view(np.uint64) == want_tot
+
+
+def test_integer_valued_dot_and_bf16_are_exact_for_any_schedule(oracle_mod):
+    """Small integers make every product and every partial sum exact in
+    binary32 (|partials| < 2^24), so every tree gives the exact result."""
+    r = rng(16)
+    n = 200_000 + 3
+    a = r.integers(-16, 17, size=n).astype(np.float32)
+    b = r.integers(-16, 17, size=n).astype(np.float32)
+    exact = float((a.astype(np.int64) * b.astype(np.int64)).sum())
+    ai = r.integers(-128, 129, size=n).astype(np.float32)
+    ab = inputs._to_bf16_bits(ai)
+    assert np.array_equal(inputs.bf16_to_f32(ab), ai)
+    exact_b = float(ai.astype(np.int64).sum())
+    a16, b16 = inputs._to_bf16_bits(a), inputs._to_bf16_bits(b)
+    for k, W in SIGMAS:
+        for acc in (0, 1):
+            assert oracle_mod.dot(a, b, k, W, acc)[1] == exact, (k, W, acc)
+            assert oracle_mod.dot(a16, b16, k, W, acc)[1] == exact, (k, W, acc)
+            assert oracle_mod.reduce(ab, k, W, acc)[1] == exact_b, (k, W, acc)
 
 
 def test_fp_tree_order_matters_pin(oracle_mod):
