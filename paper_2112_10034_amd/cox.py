@@ -523,6 +523,15 @@ class Plan:
         self.x, self.offsets = x, offsets
         wcfg = cfg if cfg is not None and any(_kw(cfg)) else _SEG_MIN_CHUNK_CFG
         nbytes = lib().cox_workspace_bytes(OP_SEGMENTED, dt, x.numel(), nseg, _cfgp(wcfg))
+        forced = os.environ.get("COX_FORCE_CFG", "")
+        if forced and (cfg is None or not any(_kw(cfg)[:2])):
+            # the library takes this schedule when the caller gives none
+            try:
+                fk = [int(v) for v in forced.split(",")][:3]
+                nbytes = max(nbytes, lib().cox_workspace_bytes(OP_SEGMENTED, dt, x.numel(), nseg,
+                                                               _cfgp(tuple(fk[:2]))))
+            except ValueError:
+                pass
         self.ws = Workspace(nbytes, x.device)  # a plan owns its workspace
         h = C.c_void_p()
         _check(lib().cox_plan_segmented(_ptr(x), dt, _ptr(offsets), nseg, x.numel(), _ptr(self.seg_total),

@@ -265,7 +265,7 @@ cox_status cox_workspace_status(void *ws, void *stream) {
     set_hip_error(e);
     return COX_ERR_HIP;
   }
-  return COX_ERR_TIMEOUT;
+  return err == ERR_LAYOUT ? COX_ERR_INVALID : COX_ERR_TIMEOUT;
 }
 
 cox_status cox_warp_shfl(const int32_t *v, int32_t *out, int64_t n, int op, int32_t arg,

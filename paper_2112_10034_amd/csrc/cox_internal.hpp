@@ -13,6 +13,11 @@ namespace cox {
 enum : int { HDR_TICKET = 0, HDR_EPOCH = 1, HDR_DONE = 2, HDR_ERR = 3, HDR_WORDS = 64 };
 constexpr size_t WS_HEADER = 256;
 
+// HDR_ERR holds the tag of a call whose bounded wait gave up; ERR_LAYOUT
+// (never a tag: tags are below 2^30) reports segment offsets whose chunks
+// exceed the workspace's capacity
+constexpr uint32_t ERR_LAYOUT = 0x80000000u;
+
 // look-back status word: [tag:30][flag:2][value:32]
 enum : uint32_t { ST_AGG = 1, ST_PREFIX = 2 };
 constexpr uint32_t TAG_MOD = (1u << 30) - 1;

@@ -36,7 +36,9 @@
 // All cross-block words carry the call's epoch tag (see scan.hip), waits
 // are bounded, and every counter is reset by its last user, so the launch
 // needs no workspace clearing and can be replayed from a graph.
+#include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 
 #include <vector>
 
@@ -119,9 +121,24 @@ __device__ __forceinline__ void seg_bounds(const int64_t *off, int64_t s, int64_
 // One block of 1024 threads: chunk counts ceil(len / S) scanned into
 // per-segment chunk starts (32-bit), the total written to hdr[SHDR_NC];
 // empty segments get total = identity and count = 0.
+//
+// Offsets that go down and up again give clamped segments that overlap,
+// and then the chunks of all segments can outnumber the workspace's
+// capacity maxch (and 32 bits).  The scan therefore adds with saturation
+// at SEG_SAT, every chunk start is clamped to maxch (a segment past the
+// capacity keeps only the chunks that fit, or none), and a total above
+// maxch sets HDR_ERR to ERR_LAYOUT.  No descriptor or status word is
+// written past maxch, and every chunk stays inside its own segment.
+constexpr uint32_t SEG_SAT = 0x7fffffffu;
+__device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {  // a, b <= SEG_SAT
+  const uint32_t r = a + b;
+  return r < SEG_SAT ? r : SEG_SAT;
+}
+
 template <int DT>
 __global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
-                                                    int64_t S, SegWS ws, void *seg_total, long long *seg_count) {
+                                                    int64_t S, uint32_t maxch, SegWS ws, void *seg_total,
+                                                    long long *seg_count) {
   __shared__ uint32_t s_w[32];
   __shared__ uint32_t s_carry;
   const int t = threadIdx.x, w = t >> 5, l = t & 31;
@@ -137,7 +154,8 @@ __global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ 
       int64_t a, b;
       seg_bounds(off, s, n, a, b);
       const int64_t len = b - a;
-      cnt = (uint32_t)((len + S - 1) / S);
+      const int64_t c64 = (len + S - 1) / S;
+      cnt = c64 < (int64_t)SEG_SAT ? (uint32_t)c64 : SEG_SAT;
       if (len == 0) {
         if (seg_total) {
           if (DT == COX_I32) ((long long *)seg_total)[s] = 0;
@@ -146,35 +164,40 @@ __global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ 
         if (seg_count) seg_count[s] = 0;
       }
     }
+    // inclusive saturating scan over the logical warp, then its exclusive
+    // form from the lane below (a saturated sum cannot be undone)
     uint32_t v = cnt;
-    v += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)v);
-    v += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)v);
-    v += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)v);
-    v += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)v);
-    v += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)v);
+    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)v));
+    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)v));
+    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)v));
+    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)v));
+    v = sat_add(v, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)v));
+    const uint32_t vup = (uint32_t)shfl_up((int)v, 1);
+    const uint32_t vex = l == 0 ? 0u : vup;
     if (l == 31) s_w[w] = v;
     __syncthreads();
     if (w == 0) {
-      uint32_t a = s_w[l];
-      uint32_t b = a;
-      b += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)b);
-      b += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)b);
-      b += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)b);
-      b += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)b);
-      b += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)b);
-      s_w[l] = b - a;  // exclusive over warps
+      uint32_t b = s_w[l];
+      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)b));
+      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)b));
+      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)b));
+      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)b));
+      b = sat_add(b, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)b));
+      const uint32_t bup = (uint32_t)shfl_up((int)b, 1);
+      s_w[l] = l == 0 ? 0u : bup;  // exclusive over warps
     }
     __syncthreads();
-    const uint32_t carry = s_carry;
-    const uint32_t excl = carry + s_w[w] + (v - cnt);
-    if (s < nseg) ws.chunk_start[s] = excl;
+    const uint32_t excl = sat_add(s_carry, sat_add(s_w[w], vex));
+    if (s < nseg) ws.chunk_start[s] = excl < maxch ? excl : maxch;
     __syncthreads();
-    if (t == 1023) s_carry = excl + cnt;
+    if (t == 1023) s_carry = sat_add(excl, cnt);
     __syncthreads();
   }
   if (t == 0) {
-    ws.chunk_start[nseg] = s_carry;
-    ws.hdr[SHDR_NC] = s_carry;
+    const uint32_t tot = s_carry, nc = tot < maxch ? tot : maxch;
+    ws.chunk_start[nseg] = nc;
+    ws.hdr[SHDR_NC] = nc;
+    if (tot > maxch) st_dev32(&ws.hdr[HDR_ERR], ERR_LAYOUT);
   }
 }
 
@@ -452,8 +475,8 @@ typedef uint32_t u32x2u __attribute__((ext_vector_type(2), aligned(4)));
 // word at all; (3) outputs.
 template <int K, int DT>
 __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__ x, const int64_t *__restrict__ off,
-                                                    int64_t nseg, int64_t n, int64_t nc_arg, SegWS ws,
-                                                    void *seg_total, uint32_t *y, uint32_t *outc,
+                                                    int64_t nseg, int64_t n, int64_t nc_arg, uint32_t maxch,
+                                                    SegWS ws, void *seg_total, uint32_t *y, uint32_t *outc,
                                                     long long *seg_count, int flags) {
   constexpr int V = K < 4 ? K : 4;
   constexpr int R = K / V;
@@ -474,7 +497,10 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   const int64_t S = (int64_t)blockDim.x * K;
   const uint32_t lt = lanemask_lt();
   const bool single = nc_arg >= 0;
-  const int64_t NC = single ? nc_arg : (int64_t)ld_dev32(&ws.hdr[SHDR_NC]);
+  // the setup pass clamps the chunk count to the workspace's capacity;
+  // the bound is repeated here so that no ticket can index past it
+  const uint32_t nc_ws = ld_dev32(&ws.hdr[SHDR_NC]);
+  const int64_t NC = single ? nc_arg : (int64_t)(nc_ws < maxch ? nc_ws : maxch);
 
   // thread tD: ticket t's chunk into slot
   auto resolve = [&](uint32_t t, int slot) {
@@ -755,8 +781,8 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   }
 }
 
-using seg_fn = void (*)(const uint32_t *, const int64_t *, int64_t, int64_t, int64_t, SegWS, void *, uint32_t *,
-                        uint32_t *, long long *, int);
+using seg_fn = void (*)(const uint32_t *, const int64_t *, int64_t, int64_t, int64_t, uint32_t, SegWS, void *,
+                        uint32_t *, uint32_t *, long long *, int);
 
 template <int DT>
 static seg_fn pick_seg_k(int k) {
@@ -789,6 +815,7 @@ struct SegCall {
   seg_fn fn;
   size_t lds;
   int grid;
+  uint32_t maxch;  // chunk capacity of the workspace layout
 };
 
 static cox_status seg_prepare(const void *x, cox_dtype dt, const int64_t *offsets, int64_t nseg, int64_t n,
@@ -833,6 +860,7 @@ static cox_status seg_prepare(const void *x, cox_dtype dt, const int64_t *offset
   sc->ws = w;
   sc->fn = fn;
   sc->lds = lds;
+  sc->maxch = (uint32_t)maxch;
   // default: as many blocks as fit, capped by the chunk bound
   sc->grid = persistent_grid((const void *)fn, block, maxch, sg.G, lds);
   return COX_OK;
@@ -843,11 +871,11 @@ static cox_status seg_launch(const SegCall &sc, hipStream_t st) {
   const int64_t S = (int64_t)block * sc.sg.k;
   if (sc.nseg == 0) return COX_OK;
   if (sc.dt == COX_I32)
-    hipLaunchKernelGGL(k_seg_setup<COX_I32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.ws,
+    hipLaunchKernelGGL(k_seg_setup<COX_I32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.maxch, sc.ws,
                        (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr,
                        (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr);
   else
-    hipLaunchKernelGGL(k_seg_setup<COX_F32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.ws,
+    hipLaunchKernelGGL(k_seg_setup<COX_F32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.maxch, sc.ws,
                        (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr,
                        (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr);
   cox_status r = launch_status();
@@ -858,7 +886,7 @@ static cox_status seg_launch(const SegCall &sc, hipStream_t st) {
   r = launch_status();
   if (r != COX_OK) return r;
   hipLaunchKernelGGL(sc.fn, dim3(sc.grid), dim3(block), sc.lds, st, (const uint32_t *)sc.x, sc.off, sc.nseg, sc.n,
-                     (int64_t)-1, sc.ws, sc.seg_total, (uint32_t *)sc.y, (uint32_t *)sc.out,
+                     (int64_t)-1, sc.maxch, sc.ws, sc.seg_total, (uint32_t *)sc.y, (uint32_t *)sc.out,
                      (long long *)sc.seg_count, sc.flags);
   return launch_status();
 }
@@ -901,6 +929,72 @@ static float time_call(const SegCall &sc, hipStream_t st, int reps) {
   hipEventDestroy(a);
   hipEventDestroy(b);
   return ms;
+}
+
+// COX_FORCE_CFG="k,W" or "k,W,G": the schedule plans use when the caller
+// gives none (no tuning)
+static bool env_cfg(cox_cfg *c) {
+  const char *v = getenv("COX_FORCE_CFG");
+  if (!v || !*v) return false;
+  int k = 0, W = 0, G = 0;
+  const int got = sscanf(v, "%d,%d,%d", &k, &W, &G);
+  if (got < 2 || k <= 0 || W <= 0 || G < 0) return false;
+  c->items_per_lane = k;
+  c->warps_per_block = W;
+  c->grid_blocks = got == 3 ? G : 0;
+  c->reserved = 0;
+  return true;
+}
+
+// Tuning cache (COX_TUNE_CACHE = path of a text file): one line per tuned
+// call shape, "<key> <k> <W> <G> <ms>", appended after tuning and read
+// before it.  The key names the operation, dtype, n, nseg, the outputs, the
+// device's architecture and compute units; the segment layout beyond
+// (n, nseg) is not part of it.
+static void tune_key(char *key, size_t len, cox_dtype dt, int64_t n, int64_t nseg, int which) {
+  int dev = 0;
+  hipDeviceProp_t pr;
+  const char *arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&pr, dev) == hipSuccess) arch = pr.gcnArchName;
+  char a[64];
+  snprintf(a, sizeof a, "%s", arch);
+  for (char *q = a; *q; q++)
+    if (*q == ' ' || *q == ':') *q = '_';
+  snprintf(key, len, "segmented/dt%d/n%lld/nseg%lld/w%d/%s/cu%d", (int)dt, (long long)n, (long long)nseg, which, a,
+           device_cus());
+}
+
+static bool tune_cache_get(const char *key, cox_cfg *c) {
+  const char *path = getenv("COX_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE *f = fopen(path, "r");
+  if (!f) return false;
+  char line[512], k[256];
+  int ki = 0, wi = 0, gi = 0;
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    if (sscanf(line, "%255s %d %d %d", k, &ki, &wi, &gi) == 4 && strcmp(k, key) == 0 && ki > 0 && wi > 0 &&
+        gi >= 0) {
+      c->items_per_lane = ki;  // the last entry for a key wins
+      c->warps_per_block = wi;
+      c->grid_blocks = gi;
+      c->reserved = 0;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void tune_cache_put(const char *key, const SegCall &sc, float ms) {
+  const char *path = getenv("COX_TUNE_CACHE");
+  if (!path || !*path) return;
+  char line[512];
+  const int len = snprintf(line, sizeof line, "%s %d %d %d %.4f\n", key, sc.sg.k, sc.sg.W, sc.grid, (double)ms);
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  if (len > 0 && len < (int)sizeof line) fwrite(line, 1, (size_t)len, f);  // one append per entry
+  fclose(f);
 }
 
 }  // namespace cox
@@ -978,7 +1072,7 @@ cox_status cox_segmented_per_segment(const void *x, cox_dtype dtype, const int64
     int grid = (int)(nc < sc.grid ? nc : sc.grid);
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(sc.fn, dim3(grid), dim3(block), sc.lds, (hipStream_t)stream, (const uint32_t *)x,
-                       offsets + s, (int64_t)1, n, nc, sc.ws, (void *)((char *)seg_total + esz * s), (uint32_t *)y,
+                       offsets + s, (int64_t)1, n, nc, sc.maxch, sc.ws, (void *)((char *)seg_total + esz * s), (uint32_t *)y,
                        (uint32_t *)out_compact, (long long *)(seg_count + s), flags);
     st = launch_status();
     if (st != COX_OK) return st;
@@ -1012,7 +1106,28 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
     hipStreamWaitEvent(p->own, ready, 0);
     hipEventDestroy(ready);
   }
-  const bool tune = autotune && (!cfg || (!cfg->items_per_lane && !cfg->warps_per_block));
+  bool tune = autotune && (!cfg || (!cfg->items_per_lane && !cfg->warps_per_block));
+  char key[256] = {0};
+  if (tune || !cfg || (!cfg->items_per_lane && !cfg->warps_per_block)) {
+    // a schedule forced by the environment, else one tuned earlier for the
+    // same call shape (the schedule fixes the float results, so a cached
+    // choice reproduces them across processes)
+    cox_cfg fc;
+    SegCall forced;
+    if (env_cfg(&fc) && seg_prepare(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count, which, &fc,
+                                    ws, ws_bytes, &forced) == COX_OK) {
+      best = forced;
+      tune = false;
+    } else if (tune) {
+      tune_key(key, sizeof key, dtype, n, nseg, which);
+      if (tune_cache_get(key, &fc) && seg_prepare(x, dtype, offsets, nseg, n, seg_total, y, out_compact, seg_count,
+                                                  which, &fc, ws, ws_bytes, &forced) == COX_OK) {
+        best = forced;
+        tune = false;
+        key[0] = 0;
+      }
+    }
+  }
   if (tune) {
     // candidate schedules and grids, timed on the caller's buffers
     static const int KW[][2] = {{16, 8}, {16, 16}, {32, 8}, {32, 16}, {8, 32}};
@@ -1036,6 +1151,7 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
         }
       }
     }
+    if (key[0] && best_ms > 0.0f) tune_cache_put(key, best, best_ms);
   }
   p->call = best;
   e = hipStreamBeginCapture(p->own, hipStreamCaptureModeRelaxed);
@@ -1060,7 +1176,10 @@ cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *off
     st = COX_ERR_HIP;
   }
   if (st == COX_OK) {
-    e = hipStreamSynchronize(p->own);
+    // one replay now, so that creation leaves the outputs written whether
+    // or not candidates were timed
+    e = hipGraphLaunch(p->exec, p->own);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->own);
     if (e != hipSuccess) {
       set_hip_error(e);
       st = COX_ERR_HIP;

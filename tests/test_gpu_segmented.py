@@ -169,3 +169,114 @@ def test_workspace_reuse_across_layouts(dev, oracle_mod):
             got = cox.segmented_per_segment(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(),
                                             torch.from_numpy(off), cfg=cfg)
             check(torch, got, oracle_mod.segmented(x, off, *cfg), off.size - 1)
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+def test_overlapping_offsets_stay_inside_the_workspace(dev, oracle_mod, dtype):
+    """Offsets that go down and up again ([0, n] five times) make five
+    overlapping segments of 10 chunks each, 50 chunks for a workspace that
+    holds n / S + nseg + 1 = 20.  The call must drop the chunks past the
+    capacity, report COX_ERR_INVALID through the workspace status, write
+    nothing past the workspace or the outputs, and leave the two segments
+    that fit with their correct totals; the workspace then serves a valid
+    call."""
+    import ctypes as C
+
+    torch, cox = dev
+    k, W = 4, 8
+    S = 32 * W * k
+    n = 10 * S
+    off = np.array([0, n] * 5, np.int64)
+    nseg = off.size - 1
+    xi, xf = inputs.segment_values(n)
+    x = xi if dtype == "i32" else xf
+    dt = cox.I32 if dtype == "i32" else cox.F32
+    cfg = cox.make_cfg(k, W)
+    L = cox.lib()
+    need = L.cox_workspace_bytes(cox.OP_SEGMENTED, dt, n, nseg, C.byref(cfg))
+    assert need > 0
+    guard = 1 << 16
+    ws = torch.empty(need + guard, dtype=torch.uint8, device="cuda")
+    ws[need:] = 0xA5
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert L.cox_workspace_init(C.c_void_p(ws.data_ptr()), need, st) == 0
+    xg = torch.from_numpy(x).cuda()
+    og = torch.from_numpy(off).cuda()
+    pad = 4096
+    sentinel = np.int32(0x5A5A5A5A)
+    y = torch.full((n + pad,), int(sentinel), dtype=torch.int32, device="cuda")
+    oc = torch.full((n + pad,), int(sentinel), dtype=torch.int32, device="cuda")
+    tot = torch.zeros(nseg, dtype=torch.int64 if dtype == "i32" else torch.float64, device="cuda")
+    cnt = torch.zeros(nseg, dtype=torch.int64, device="cuda")
+    print("overlapping offsets", dtype, flush=True)
+    rc = L.cox_segmented(C.c_void_p(xg.data_ptr()), dt, C.c_void_p(og.data_ptr()), nseg, n,
+                         C.c_void_p(tot.data_ptr()), C.c_void_p(y.data_ptr()), C.c_void_p(oc.data_ptr()),
+                         C.c_void_p(cnt.data_ptr()), 7, C.byref(cfg), C.c_void_p(ws.data_ptr()), need, st)
+    assert rc == 0
+    assert L.cox_workspace_status(C.c_void_p(ws.data_ptr()), st) == 1  # COX_ERR_INVALID
+    assert L.cox_workspace_status(C.c_void_p(ws.data_ptr()), st) == 0  # the flag was cleared
+    assert bool((ws[need:] == 0xA5).all()), "bytes written past the workspace"
+    assert bool((y[n:] == int(sentinel)).all()) and bool((oc[n:] == int(sentinel)).all()), \
+        "bytes written past the outputs"
+    # segments 0 and 2 are the first 20 chunks, which fit: their totals are
+    # those of x[0, n) alone
+    wt, _, _, _ = oracle_mod.segmented(x, np.array([0, n], np.int64), k, W)
+    t = tot.cpu().numpy()
+    assert np.array_equal(bits(t[[0, 2]]), bits(np.array([wt[0], wt[0]])))
+    # the same workspace then serves a valid call
+    off2 = np.array([0, 3, n // 2, n], np.int64)
+    og2 = torch.from_numpy(off2).cuda()
+    tot2 = torch.zeros(3, dtype=tot.dtype, device="cuda")
+    y2 = torch.empty_like(xg)
+    oc2 = torch.zeros_like(xg)
+    cnt2 = torch.zeros(3, dtype=torch.int64, device="cuda")
+    rc = L.cox_segmented(C.c_void_p(xg.data_ptr()), dt, C.c_void_p(og2.data_ptr()), 3, n,
+                         C.c_void_p(tot2.data_ptr()), C.c_void_p(y2.data_ptr()), C.c_void_p(oc2.data_ptr()),
+                         C.c_void_p(cnt2.data_ptr()), 7, C.byref(cfg), C.c_void_p(ws.data_ptr()), need, st)
+    assert rc == 0
+    assert L.cox_workspace_status(C.c_void_p(ws.data_ptr()), st) == 0
+    check(torch, (tot2, y2, oc2, cnt2), oracle_mod.segmented(x, off2, k, W), 3)
+
+
+def test_plan_creation_writes_the_outputs(dev, oracle_mod):
+    """A plan with a given schedule (nothing tuned) leaves the call's
+    results in its outputs when creation returns."""
+    torch, cox = dev
+    off, _, xf = small_case()
+    xg, og = torch.from_numpy(xf).cuda(), torch.from_numpy(off).cuda()
+    plan = cox.Plan(xg, og, 7, cfg=(4, 8), autotune=False)
+    torch.cuda.synchronize()
+    check(torch, (plan.seg_total, plan.y, plan.out, plan.seg_count), oracle_mod.segmented(xf, off, 4, 8),
+          off.size - 1)
+    plan.close()
+
+
+def test_plan_forced_schedule_and_tuning_cache(dev, oracle_mod, tmp_path, monkeypatch):
+    """COX_FORCE_CFG fixes a plan's schedule without tuning; COX_TUNE_CACHE
+    records a tuned schedule and a later plan of the same call shape reuses
+    it (so the float results repeat across processes)."""
+    torch, cox = dev
+    off, _, xf = small_case()
+    xg, og = torch.from_numpy(xf).cuda(), torch.from_numpy(off).cuda()
+    monkeypatch.setenv("COX_FORCE_CFG", "2,8")
+    plan = cox.Plan(xg, og, 7, autotune=True)
+    assert plan.cfg()[:2] == (2, 8)
+    check(torch, plan.execute(), oracle_mod.segmented(xf, off, 2, 8), off.size - 1)
+    plan.close()
+    monkeypatch.delenv("COX_FORCE_CFG")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("COX_TUNE_CACHE", str(cache))
+    p1 = cox.Plan(xg, og, 7, autotune=True)
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("segmented/dt2/")
+    k, W, G = p1.cfg()
+    assert [int(v) for v in lines[0].split()[1:4]] == [k, W, G]
+    p1.close()
+    # a planted entry for the same key is taken as is, without tuning
+    key = lines[0].split()[0]
+    cache.write_text(lines[0] + "\n" + f"{key} 4 32 {G} 0.0\n")
+    p2 = cox.Plan(xg, og, 7, autotune=True)
+    assert p2.cfg() == (4, 32, G)
+    assert len(cache.read_text().splitlines()) == 2
+    check(torch, p2.execute(), oracle_mod.segmented(xf, off, 4, 32), off.size - 1)
+    p2.close()
