@@ -96,6 +96,10 @@ typedef struct {
   int32_t reserved;
 } cox_cfg;
 
+/* ---------------------------------------------------------------------
+ * Library plumbing (status text, versions, schedules, workspaces): no
+ * passage of the paper defines these.
+ * ------------------------------------------------------------------- */
 const char *cox_status_string(cox_status s);
 /* hipError_t of the most recent COX_ERR_HIP on the calling thread */
 int cox_last_hip_error(void);
@@ -113,8 +117,10 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
 cox_status cox_workspace_init(void *ws, size_t ws_bytes, void *stream);
 /* Synchronises `stream`, then reports COX_ERR_TIMEOUT if a bounded
  * cross-block wait of a call that used this workspace gave up since the
- * previous check (the results of that call are invalid), and clears the
- * flag.  COX_OK otherwise. */
+ * previous check (the results of that call are invalid), or
+ * COX_ERR_INVALID if a segmented call's offsets overlapped so that their
+ * chunks outnumbered the workspace's capacity (those results are invalid
+ * too), and clears the flag.  COX_OK otherwise. */
 cox_status cox_workspace_status(void *ws, void *stream);
 
 /* ---------------------------------------------------------------------
@@ -165,7 +171,11 @@ cox_status cox_warp_vote(const int32_t *pred, const uint32_t *mask, int64_t n, u
 cox_status cox_warp_reduce_blocks_i32(const int32_t *x, int64_t n, int32_t *block_sums,
                                       int32_t *warp_pos_count, void *stream);
 
-/* Chunked sum of x under schedule cfg (see cox_cfg).
+/* Chunked sum of x under schedule cfg (see cox_cfg): the warp-shuffle
+ * reduction of Code 1 (Sec. 2.3) inside every block, as in the SDK
+ * reduction kernels reduce4-6 / reduce / reduceFinal of Table 1, with the
+ * compensated variant and the FP64 final combine of this library (the
+ * paper does not discuss floating-point accuracy).
  * dtype COX_I32 (acc must be PLAIN): lanes, warps and blocks add with
  *   two's-complement wrap (CUDA int); chunk partials are int32;
  *   *total (int64) = sum of the chunk partials as int64, which equals the
@@ -185,8 +195,9 @@ cox_status cox_warp_reduce(const void *x, cox_dtype dtype, int64_t n, cox_acc ac
                            const cox_cfg *cfg, void *chunk_partials, void *total, void *ws,
                            size_t ws_bytes, void *stream);
 
-/* Chunked dot product sum_i a_i * b_i (dtype COX_F32 or COX_BF16) with the
- * schedule of cox_warp_reduce.  PLAIN: s = fmaf(a_i, b_i, s) per element.
+/* Chunked dot product sum_i a_i * b_i (dtype COX_F32 or COX_BF16), the
+ * gpuDotProduct kernel of Table 1 (a warp cooperative-group reduction,
+ * Sec. 2.2.2), with the schedule of cox_warp_reduce.  PLAIN: s = fmaf(a_i, b_i, s) per element.
  * TWOSUM (Dot2): (p, pe) = TwoProduct(a_i, b_i) = (a*b, fmaf(a, b, -p)),
  * (s, q) = TwoSum(s, p), c = c + (pe + q).  Padding: a = -0.0, b = +0.0.
  * Result in *total (device double); partials as for cox_warp_reduce. */
@@ -194,17 +205,21 @@ cox_status cox_warp_dot(const void *a, const void *b, cox_dtype dtype, int64_t n
                         const cox_cfg *cfg, void *chunk_partials, double *total, void *ws,
                         size_t ws_bytes, void *stream);
 
-/* Inclusive int32 scan, y_i = (x_0 + ... + x_i) mod 2^32, in one pass:
- * warp scans with shfl_up (Kogge-Stone), warp totals combined in shared
- * memory, chunks chained by decoupled look-back (status words published
+/* Inclusive int32 scan (the shuffle scan of the CUDA sample whose
+ * shfl_scan_test and uniform_add kernels Table 1 lists; shfl_up is one of
+ * the warp shuffles of Sec. 2.2.1), y_i = (x_0 + ... + x_i) mod 2^32, in
+ * one pass: warp scans with shfl_up (Kogge-Stone), warp totals combined in
+ * shared memory (the block-level carry that uniform_add applies), chunks chained by decoupled look-back (status words published
  * with device-scope atomics; chunk order from a ticket counter so that a
  * chunk only waits for chunks already being processed).  x, y: int32[n]
  * device buffers (may not overlap); ws: cox_workspace_bytes(COX_OP_SCAN). */
 cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg *cfg, void *ws,
                          size_t ws_bytes, void *stream);
 
-/* Stable compaction keeping x_i > 0: out[0 .. *count) = the kept elements
- * in input order; *count (device int64) = their number.  Per warp and row
+/* Stable ballot compaction (warp votes, Sec. 2.2.1; the filtering that
+ * the filter_arr kernel of Table 1 performs, here with a static full mask
+ * and ballot ranks instead of its dynamic group), keeping x_i > 0:
+ * out[0 .. *count) = the kept elements in input order; *count (device int64) = their number.  Per warp and row
  * the ranks come from ballots: rank = popc(ballot & lanemask_lt) summed
  * over the lane's vector slots; warp counts are scanned in shared memory
  * and chunk offsets chained by decoupled look-back.  x: int32[n]; out:
@@ -212,7 +227,9 @@ cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg 
 cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t *count,
                               const cox_cfg *cfg, void *ws, size_t ws_bytes, void *stream);
 
-/* Sorts every group of `tile` consecutive keys ascending (unsigned) with a
+/* Tile sort, a workload built from the warp shuffles of Sec. 2.2.1
+ * (__shfl_xor_sync exchanges) over thread-block tiles of Sec. 2.2.2:
+ * sorts every group of `tile` consecutive keys ascending (unsigned) with a
  * bitonic network.  tile = 32: the cross-lane steps are __shfl_xor_sync
  * exchanges inside the group, cfg->items_per_lane keys per lane (1, 2, 4,
  * 8 or 16; 0 = 4).  tile = 64 .. 1024 (a power of two): the group spans
@@ -225,8 +242,9 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
 cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t n, int tile,
                          const cox_cfg *cfg, void *stream);
 
-/* Key-value form (a workload built from the same shuffle network): every
- * group of 32 consecutive pairs (keys[i], vals[i]) ordered by unsigned key,
+/* Key-value form (a workload built from the same shuffle network: warp
+ * shuffles, Sec. 2.2.1, over 32-lane tiles, Sec. 2.2.2): every group of 32
+ * consecutive pairs (keys[i], vals[i]) ordered by unsigned key,
  * pairs with equal keys in their original order (a stable sort, so the
  * result is unique).  The network sorts (key, position in the group);
  * each output then takes the value at its position.  A partial last group
@@ -248,8 +266,9 @@ cox_status cox_tile_sort_kv(const uint32_t *keys, const uint32_t *vals, uint32_t
  * aligned); out: int32[ceil(n/T)]; device buffers. */
 cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, void *stream);
 
-/* Masked (divergent) warp operations with predicate-derived masks, n % 32
- * == 0.  Lane l of warp g, x = x[32g + l]:
+/* Masked (divergent) warp operations with predicate-derived masks (the
+ * mask argument of the warp shuffles and votes, Sec. 2.2.1; COX itself
+ * supports only static full masks, Sec. 2.2.3), n % 32 == 0.  Lane l of warp g, x = x[32g + l]:
  *   p = ((uint32)x & 1023) < density;  m = __ballot_sync(FULL, p);
  *   if (p) { b = __ballot_sync(m, x > 0); A = __any_sync(m, ((x >> 10) & 31) == 0);
  *            L = __all_sync(m, ((x >> 15) & 31) != 0);
@@ -299,7 +318,11 @@ cox_status cox_warp_dynamic(const int32_t *x, int64_t n, int density, uint32_t *
  * non-decreasing, within [0, n]; x: device int32 or float32 [n], 16-byte
  * aligned).  Offsets cannot be checked before launch; the kernels clamp
  * every segment to [0, n] (a reversed segment is empty), so bad offsets
- * give meaningless results but no access outside x.  Chunks of
+ * give meaningless results but no access outside x, y, out_compact or the
+ * workspace.  Offsets that go down and up again make overlapping
+ * segments; when their chunks outnumber the workspace's capacity
+ * (n / S + nseg + 1), the chunks past it are dropped and
+ * cox_workspace_status reports COX_ERR_INVALID.  Chunks of
  * S = 32 * warps_per_block * items_per_lane elements start at each
  * segment's first element (items_per_lane <= 32).
  *   seg_total[s] : device int64 (int32 input) = sum of the int32-wrapped
@@ -340,15 +363,26 @@ cox_status cox_segmented_per_segment(const void *x, cox_dtype dtype, const int64
                                      size_t ws_bytes, void *stream);
 
 /* A plan: one segmented call bound to its buffers and captured in a
- * hipGraph on a stream of the plan's own.  With autotune != 0 and no
- * schedule given (cfg NULL or items/warps zero), creation first runs the
- * call for a set of candidate (items_per_lane, warps_per_block, grid)
- * and keeps the fastest; the chosen schedule (which fixes the float
- * results) is reported by cox_plan_get_cfg.  Creation runs the call
- * (outputs are overwritten) and synchronises; ws must be large enough for
- * every candidate tried (candidates that do not fit are skipped).
- * cox_plan_execute replays the graph on `stream`; a plan must not run
- * concurrently with itself or with another call on the same workspace. */
+ * hipGraph on a stream of the plan's own (the batched form of the
+ * per-launch fork/join that Sec. 4 describes; this is the plan that a
+ * general cox_plan_create(op, ...) would build for the segmented
+ * operations, the only ones that need one).  The schedule, when the
+ * caller gives none (cfg NULL or items/warps zero), is, in this order:
+ *  - COX_FORCE_CFG="k,W" or "k,W,G" from the environment, if it is valid;
+ *  - with autotune != 0 and COX_TUNE_CACHE naming a file: the last entry
+ *    of that file for this call shape (operation, dtype, n, nseg, outputs,
+ *    device architecture and compute units);
+ *  - with autotune != 0: the fastest of a set of candidate
+ *    (items_per_lane, warps_per_block, grid), each timed on the caller's
+ *    buffers; the choice is appended to COX_TUNE_CACHE when it is set;
+ *  - otherwise the default schedule.
+ * The chosen schedule (which fixes the float results) is reported by
+ * cox_plan_get_cfg.  Creation replays the captured graph once, so the
+ * outputs hold the call's results, and synchronises; ws must be large
+ * enough for every candidate tried (candidates that do not fit are
+ * skipped).  cox_plan_execute replays the graph on `stream`; a plan must
+ * not run concurrently with itself or with another call on the same
+ * workspace. */
 typedef struct cox_plan_s *cox_plan;
 cox_status cox_plan_segmented(const void *x, cox_dtype dtype, const int64_t *offsets, int64_t nseg, int64_t n,
                               void *seg_total, void *y, void *out_compact, int64_t *seg_count, int which,
@@ -462,7 +496,8 @@ cox_status cox_cg_solve_per_phase(const int32_t *row_ptr, const int32_t *col_idx
                                   void *stream);
 
 /* ---------------------------------------------------------------------
- * Bandwidth reference kernels (not part of the method): a plain read and
+ * Bandwidth reference kernels (measurement plumbing, not part of the
+ * method, so no passage of the paper defines them): a plain read and
  * a plain copy with 16-byte accesses.  They give the achievable HBM
  * ceiling and the known-size reference for hardware byte counters.
  * bytes % 16 == 0; pointers 16-byte aligned; grid_blocks 0 = fill the

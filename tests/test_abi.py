@@ -137,3 +137,47 @@ def test_widened_entry_points_reject_bad_arguments_before_launch(cox):
     assert cg(*args, C.byref(cox.make_cfg(3, 32)), P(256), 1 << 30, None) == 1
     assert cg(*args, None, P(256), 64, None) == 5
     assert L.cox_cg_solve_per_phase(*args, None, P(256), 64, None) == 5
+
+
+def _declarations_with_context():
+    """(name, own comment, section banner) for every cox_ function declared
+    in include/cox.h, in order."""
+    import re
+
+    src = open(os.path.join(ROOT, "include", "cox.h")).read()
+    banner, last, out = "", "", []
+    for m in re.finditer(r"/\*.*?\*/|^[A-Za-z_][\w \*]*?\b(cox_\w+)\s*\(", src, re.S | re.M):
+        t = m.group(0)
+        if t.startswith("/*"):
+            t = re.sub(r"\n\s*\*(?!/)", " ", t)
+            if t.startswith("/* ----"):
+                banner, last = t, ""
+            else:
+                last = t
+        else:
+            out.append((m.group(1), last, banner))
+    return out
+
+
+def test_every_declaration_cites_its_passage():
+    """Every entry point's comment (or the banner of its section) cites the
+    paper's section, table or code listing it follows, or says that no
+    passage of the paper defines it (plumbing and measurement kernels)."""
+    import re
+
+    cite = re.compile(r"(Sec\.|[Ss]ection|Table|Code|Appendix|Algorithm)\s*~?\d")
+    decls = _declarations_with_context()
+    assert len(decls) >= 30
+    missing = []
+    for name, own, banner in decls:
+        ctx = own + banner
+        if not (cite.search(ctx) or "no passage of the paper" in " ".join(ctx.split())):
+            missing.append(name)
+    assert not missing, f"declarations without a cited passage: {missing}"
+    # the compute entry points cite a passage of their own or of their section
+    compute = [d for d in decls if not re.search(r"no passage of the paper", " ".join((d[1] + d[2]).split()))]
+    assert {"cox_warp_scan", "cox_ballot_compact", "cox_tile_sort", "cox_tile_sort_kv",
+            "cox_warp_masked", "cox_warp_reduce", "cox_warp_dot"} <= {d[0] for d in compute}
+    for name in ("cox_warp_scan", "cox_ballot_compact", "cox_tile_sort", "cox_tile_sort_kv", "cox_warp_masked"):
+        own = next(d[1] for d in decls if d[0] == name)
+        assert cite.search(own), f"{name} has no citation of its own"
