@@ -24,19 +24,36 @@ def dev():
 
 
 def runs_valid(filt, x, D):
-    """filt holds every warp's members as one run in rank order."""
+    """filt holds every warp's members as one run in rank order, the runs
+    disjoint and together covering filt: walking filt from the start, each
+    position begins the run of a warp not yet used whose first member has
+    that value and whose whole run matches there; the walk must use every
+    warp with members exactly once and end at the end of filt."""
     members = (x.view(np.uint32) & 1023) < D
+    assert filt.size == int(members.sum())
     assert np.array_equal(np.sort(filt), np.sort(x[members]))
-    xs, ps = x.reshape(-1, 32), members.reshape(-1, 32)
-    # runs are consecutive: walk the output warp by warp through a position map
-    start = {}
-    for i, v in enumerate(filt):
-        start.setdefault(int(v), []).append(i)
-    for g in range(xs.shape[0]):
-        run = xs[g][ps[g]]
-        if run.size == 0:
-            continue
-        assert any(np.array_equal(filt[h:h + run.size], run) for h in start[int(run[0])])
+    ps = members.reshape(-1, 32)
+    cnt = ps.sum(1)
+    allv = x[members]  # the runs, concatenated in warp order
+    start = np.concatenate(([0], np.cumsum(cnt)[:-1]))
+    warps = np.nonzero(cnt)[0]
+    cand = {}
+    for w, v in zip(warps.tolist(), allv[start[warps]].tolist()):
+        cand.setdefault(v, []).append(w)
+    total, p = filt.size, 0
+    while p < total:
+        lst = cand.get(int(filt[p]))
+        assert lst, f"position {p} starts no warp's run"
+        for i, w in enumerate(lst):
+            c = int(cnt[w])
+            if p + c <= total and np.array_equal(filt[p:p + c], allv[start[w]:start[w] + c]):
+                lst.pop(i)
+                p += c
+                break
+        else:
+            raise AssertionError(f"no unused warp's run matches at position {p}")
+    assert p == total
+    assert not any(cand.values()), "some warps' runs are missing"
 
 
 @pytest.mark.parametrize("D", (0, 1, 102, 512, 922, 1024))
