@@ -280,3 +280,34 @@ def test_plan_forced_schedule_and_tuning_cache(dev, oracle_mod, tmp_path, monkey
     assert len(cache.read_text().splitlines()) == 2
     check(torch, p2.execute(), oracle_mod.segmented(xf, off, 4, 32), off.size - 1)
     p2.close()
+
+
+def test_per_segment_launches_captured_in_a_graph(dev, oracle_mod):
+    """The per-segment baseline's launches (a workspace clear, then one
+    launch per segment) captured in one graph: every replay, with eager
+    work between replays, gives the oracle's results."""
+    torch, cox = dev
+    off, _, xf = small_case()
+    xg, og, oh = torch.from_numpy(xf).cuda(), torch.from_numpy(off).cuda(), torch.from_numpy(off)
+    nseg = off.size - 1
+    tot = torch.zeros(nseg, dtype=torch.float64, device="cuda")
+    y, oc = torch.zeros_like(xg), torch.zeros_like(xg)
+    cnt = torch.zeros(nseg, dtype=torch.int64, device="cuda")
+
+    def run():
+        cox.segmented_per_segment(xg, og, oh, cfg=(8, 8), seg_total=tot, y=y, out=oc, seg_count=cnt)
+    run()  # the workspace and the kernel are set up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="relaxed"):
+        run()
+    want = oracle_mod.segmented(xf, off, 8, 8)
+    for _ in range(3):
+        for t in (tot, y, oc, cnt):
+            t.zero_()
+        junk = torch.randn(1 << 16, device="cuda").sum()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check(torch, (tot, y, oc, cnt), want, nseg)
+        assert torch.isfinite(junk)
