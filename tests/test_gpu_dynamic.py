@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2112_10034_amd import inputs
+from runs_check import runs_partition
 
 pytestmark = pytest.mark.gpu
 
@@ -24,36 +25,14 @@ def dev():
 
 
 def runs_valid(filt, x, D):
-    """filt holds every warp's members as one run in rank order, the runs
-    disjoint and together covering filt: walking filt from the start, each
-    position begins the run of a warp not yet used whose first member has
-    that value and whose whole run matches there; the walk must use every
-    warp with members exactly once and end at the end of filt."""
+    """The appended members of every 32-lane warp form one run in rank
+    order, the runs disjoint and together covering filt."""
     members = (x.view(np.uint32) & 1023) < D
     assert filt.size == int(members.sum())
     assert np.array_equal(np.sort(filt), np.sort(x[members]))
-    ps = members.reshape(-1, 32)
-    cnt = ps.sum(1)
-    allv = x[members]  # the runs, concatenated in warp order
-    start = np.concatenate(([0], np.cumsum(cnt)[:-1]))
-    warps = np.nonzero(cnt)[0]
-    cand = {}
-    for w, v in zip(warps.tolist(), allv[start[warps]].tolist()):
-        cand.setdefault(v, []).append(w)
-    total, p = filt.size, 0
-    while p < total:
-        lst = cand.get(int(filt[p]))
-        assert lst, f"position {p} starts no warp's run"
-        for i, w in enumerate(lst):
-            c = int(cnt[w])
-            if p + c <= total and np.array_equal(filt[p:p + c], allv[start[w]:start[w] + c]):
-                lst.pop(i)
-                p += c
-                break
-        else:
-            raise AssertionError(f"no unused warp's run matches at position {p}")
-    assert p == total
-    assert not any(cand.values()), "some warps' runs are missing"
+    cnt = members.reshape(-1, 32).sum(1)
+    ok, why = runs_partition(filt, x[members], cnt)
+    assert ok, why
 
 
 @pytest.mark.parametrize("D", (0, 1, 102, 512, 922, 1024))
