@@ -80,11 +80,46 @@ __global__ __launch_bounds__(256) void k_tile_reduce(const int32_t *__restrict__
   }
 }
 
-// v with lane 32 replaced by the wave-uniform value u (v_writelane writes
+// v with lane `lane` replaced by the wave-uniform value u (v_writelane writes
 // one lane of a vector register, whatever the execution mask)
-__device__ __forceinline__ uint32_t with_lane32(uint32_t v, uint32_t u) {
-  asm volatile("v_writelane_b32 %0, %1, 32" : "+v"(v) : "s"(__builtin_amdgcn_readfirstlane((int)u)));
+template <int L>
+__device__ __forceinline__ uint32_t with_lane(uint32_t v, uint32_t u) {
+  asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(__builtin_amdgcn_readfirstlane((int)u)), "i"(L));
   return v;
+}
+
+// row r of a wave's round of masked operations (see k_warp_masked): the
+// two warps' record values go to lanes 2r and 2r + 1 of rm (mask), rb
+// (ballot of x > 0), ra / rl (the any / all ballots within the mask) and
+// rc (leader value); the flags word is formed from them once per round
+template <int r, int R>
+__device__ __forceinline__ void masked_rows(const int32_t (&xs)[R], int32_t *__restrict__ dst, uint32_t D,
+                                            uint32_t hib, uint32_t lp1, uint32_t &rm, uint32_t &rb, uint32_t &ra,
+                                            uint32_t &rl, uint32_t &rc) {
+  if constexpr (r < R) {
+    const int32_t xv = xs[r];
+    const bool p = ((uint32_t)xv & 1023u) < D;
+    const uint64_t P = __builtin_amdgcn_ballot_w64(p);
+    const uint64_t Bq = __builtin_amdgcn_ballot_w64(xv > 0) & P;
+    const uint64_t Aq = __builtin_amdgcn_ballot_w64((xv & 0x7c00) == 0) & P;
+    const uint64_t Lq = __builtin_amdgcn_ballot_w64((xv & 0xf8000) != 0) & P;
+    // m = this half's mask; lanes outside m read some lane and discard it
+    // (m == 0 leaves the count undefined, and every such lane discards)
+    const uint32_t m = (uint32_t)(P >> hib);
+    const uint32_t c = (uint32_t)__builtin_ctz(__builtin_amdgcn_alignbit(m, m, lp1));
+    const int32_t sv = bperm(xv, (int)(((c + lp1) & 31u) | hib));
+    dst[r * 64] = p ? sv : INT32_MIN;
+    const uint32_t m0 = (uint32_t)P, m1 = (uint32_t)(P >> 32);
+    // leader values read unconditionally (no branch), zero for an empty warp
+    const uint32_t bl0 = (uint32_t)__builtin_amdgcn_readlane(xv, m0 ? __builtin_ctz(m0) : 0);
+    const uint32_t bl1 = (uint32_t)__builtin_amdgcn_readlane(xv, 32 + (m1 ? __builtin_ctz(m1) : 0));
+    rm = with_lane<2 * r + 1>(with_lane<2 * r>(rm, m0), m1);
+    rb = with_lane<2 * r + 1>(with_lane<2 * r>(rb, (uint32_t)Bq), (uint32_t)(Bq >> 32));
+    ra = with_lane<2 * r + 1>(with_lane<2 * r>(ra, (uint32_t)Aq), (uint32_t)(Aq >> 32));
+    rl = with_lane<2 * r + 1>(with_lane<2 * r>(rl, (uint32_t)Lq), (uint32_t)(Lq >> 32));
+    rc = with_lane<2 * r + 1>(with_lane<2 * r>(rc, m0 ? bl0 : 0u), m1 ? bl1 : 0u);
+    masked_rows<r + 1, R>(xs, dst, D, hib, lp1, rm, rb, ra, rl, rc);
+  }
 }
 
 // The masked operations without a divergent branch: every ballot is taken
@@ -93,67 +128,46 @@ __device__ __forceinline__ uint32_t with_lane32(uint32_t v, uint32_t u) {
 // and leader broadcast are derived from the half of that value, and every
 // lane computes its shuffle; lanes outside m then store INT32_MIN instead.
 // The stored values are those of the divergent CUDA code, whose lanes of m
-// are exactly the lanes that would execute it.  Both warps' records are
-// computed from the wave-uniform values; logical lane 0 of each warp
-// writes its warp's (the same bytes as writing it from the leader).
+// are exactly the lanes that would execute it.
+//
+// A wave owns 64R consecutive elements per round (row r: elements
+// 64r .. 64r + 63, the logical warps 2r and 2r + 1 of the wave), so one
+// base address serves every row.  The next lane of m above l, wrapping, is
+// the first set bit of m rotated right by l + 1, counted from lane l + 1.
+// The 2R records of a round are gathered in lanes 0 .. 2R - 1 (lane 2r + h
+// holds warp 2r + h's values, written with v_writelane from the
+// wave-uniform ballots), their flag words formed there, and stored as one
+// contiguous run of 16-byte vectors.
 template <int R>
 __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__ x, int64_t n, int D,
                                                      int32_t *__restrict__ out, uint32_t *__restrict__ rec) {
-  const int t = threadIdx.x, l = t & 31;
-  const bool hi = (t & 32) != 0;
-  const int64_t per_block = 256 * R;
+  static_assert(2 * R <= 64, "records of a round fit in one wave");
+  const int t = threadIdx.x, l = t & 31, lane = t & 63;
+  const uint32_t hib = (uint32_t)(t & 32);  // first lane of the caller's half
+  const uint32_t lp1 = (uint32_t)l + 1u;
+  const int64_t per_wave = 64 * R;
+  const int64_t per_block = 4 * per_wave;
   const int64_t stride = (int64_t)gridDim.x * per_block;
   const int64_t rounds = (n + stride - 1) / stride;
-  // lanes of m above l: m & ~(2^(l+1) - 1)
-  const uint32_t above_mask = l == 31 ? 0u : (FULL << (l + 1));
   for (int64_t it = 0; it < rounds; it++) {
-    const int64_t base = it * stride + (int64_t)blockIdx.x * per_block;
-    if (base + per_block <= n) {
-      const int32_t *src = x + base + t;
-      int32_t *dst = out + base + t;
-      uint32_t *rdst = rec + 4 * ((base + t) >> 5);  // lanes 0 and 32: their warp's record
+    const int64_t wbase = it * stride + (int64_t)blockIdx.x * per_block + (t >> 6) * per_wave;
+    if (wbase + per_wave <= n) {
+      const int32_t *src = x + wbase + lane;
+      int32_t *dst = out + wbase + lane;
       int32_t xs[R];
 #pragma unroll
-      for (int r = 0; r < R; r++) xs[r] = (int32_t)ld_stream1(src + r * 256);
-#pragma unroll
-      for (int r = 0; r < R; r++) {
-        const int32_t xv = xs[r];
-        const bool p = ((uint32_t)xv & 1023u) < (uint32_t)D;
-        const uint64_t P = __builtin_amdgcn_ballot_w64(p);
-        const uint64_t Bq = __builtin_amdgcn_ballot_w64(xv > 0) & P;
-        const uint64_t Aq = __builtin_amdgcn_ballot_w64((xv & 0x7c00) == 0) & P;
-        const uint64_t Lq = __builtin_amdgcn_ballot_w64((xv & 0xf8000) != 0) & P;
-        const uint32_t m0 = (uint32_t)P, m1 = (uint32_t)(P >> 32);
-        const uint32_t m = hi ? m1 : m0;
-        // next lane of m above l, wrapping to its first lane (lanes outside
-        // m read some lane of their half and discard it)
-        const uint32_t above = m & above_mask;
-        const uint32_t sm = above ? above : m;
-        const int sl = sm ? __builtin_ctz(sm) : 0;
-        const int32_t sv = bperm(xv, (hi ? 32 : 0) + sl);
-        dst[r * 256] = p ? sv : INT32_MIN;
-        if (l == 0) {
-          // both warps' records from wave-uniform values: lane 0 stores the
-          // lower warp's, lane 32 (set by v_writelane) the upper warp's
-          const int ld0 = m0 ? __builtin_ctz(m0) : 0, ld1 = m1 ? __builtin_ctz(m1) : 0;
-          const uint32_t bc0 = m0 ? (uint32_t)__builtin_amdgcn_readlane(xv, ld0) : 0u;
-          const uint32_t bc1 = m1 ? (uint32_t)__builtin_amdgcn_readlane(xv, 32 + ld1) : 0u;
-          const uint32_t f0 = m0 ? (((uint32_t)Aq != 0u) | ((uint32_t)((uint32_t)Lq == m0) << 1)) : 0u;
-          const uint32_t f1 = m1 ? (((uint32_t)(Aq >> 32) != 0u) | ((uint32_t)((uint32_t)(Lq >> 32) == m1) << 1)) : 0u;
-          uint4 v;
-          v.x = with_lane32(m0, m1);
-          v.y = with_lane32((uint32_t)Bq, (uint32_t)(Bq >> 32));
-          v.z = with_lane32(f0, f1);
-          v.w = with_lane32(bc0, bc1);
-          *(uint4 *)(rdst + r * 32) = v;
-        }
-      }
+      for (int r = 0; r < R; r++) xs[r] = (int32_t)ld_stream1(src + r * 64);
+      uint32_t rm = 0u, rb = 0u, ra = 0u, rl = 0u, rc = 0u;
+      masked_rows<0, R>(xs, dst, (uint32_t)D, hib, lp1, rm, rb, ra, rl, rc);
+      // flags: any in bit 0, all in bit 1 (an empty warp's record is zero)
+      const uint32_t rf = (ra != 0u ? 1u : 0u) | (rm != 0u && rl == rm ? 2u : 0u);
+      if (lane < 2 * R) *(uint4 *)(rec + 4 * ((wbase >> 5) + lane)) = make_uint4(rm, rb, rf, rc);
     } else {
       // partial last round: whole logical warps only (n % 32 == 0), so a
       // warp is either entirely in range or entirely out
 #pragma unroll 1
       for (int r = 0; r < R; r++) {
-        const int64_t e = base + r * 256 + t;
+        const int64_t e = wbase + r * 64 + lane;
         const int64_t e32 = e & ~(int64_t)31;
         if (e32 >= n) continue;  // uniform per logical warp
         const int32_t xv = (int32_t)ld_stream1(x + e);
@@ -162,7 +176,7 @@ __global__ __launch_bounds__(256) void k_warp_masked(const int32_t *__restrict__
         const uint32_t b = ballot(xv > 0) & m;
         const uint32_t A = (ballot(((xv >> 10) & 31) == 0) & m) != 0u;
         const uint32_t L = (ballot(((xv >> 15) & 31) != 0) & m) == m;
-        const uint32_t above = m & above_mask;
+        const uint32_t above = m & (l == 31 ? 0u : (FULL << (l + 1)));
         const int sl = above ? __builtin_ctz(above) : (m ? __builtin_ctz(m) : l);
         const int32_t sv = shfl(xv, sl);
         const int32_t bc = shfl(xv, m ? __builtin_ctz(m) : 0);
