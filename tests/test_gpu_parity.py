@@ -241,7 +241,7 @@ def test_tile_sort_adversarial_and_zero_one(dev):
             assert np.array_equal(got, np.sort(c.reshape(-1, 32), axis=1).reshape(-1))
 
 
-@pytest.mark.parametrize("k", [4, 1])
+@pytest.mark.parametrize("k", [4, 1, 8, 16])
 def test_tile_sort_all_zero_one_groups(dev, k):
     """The 0-1 principle (Knuth, TAOCP vol. 3, 5.3.4): a comparator network
     sorts every input iff it sorts every 0/1 input.  All 2^32 0/1 patterns
