@@ -216,6 +216,30 @@ cox_status cox_warp_dot(const void *a, const void *b, cox_dtype dtype, int64_t n
 cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg *cfg, void *ws,
                          size_t ws_bytes, void *stream);
 
+/* Size of the device scratch that cox_warp_scan_noalloc uses (1 MiB). */
+#define COX_NOALLOC_SCRATCH_BYTES ((size_t)1 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cox_warp_scan with the same arguments, result and kernels, but without a
+ * workspace argument.  The look-back header and status words live in a
+ * library-owned device array of COX_NOALLOC_SCRATCH_BYTES, one per device,
+ * held until the process ends; the call allocates nothing (no hipMalloc,
+ * no allocating library routine).  The first call on a device looks the
+ * array up and zeroes it on `stream`, ahead of its own kernels.
+ * Limit: cox_workspace_bytes(COX_OP_SCAN, COX_I32, n, 0, cfg) must not
+ * exceed COX_NOALLOC_SCRATCH_BYTES (the default schedule covers every n
+ * the scan accepts; the smallest schedule, 32 elements per chunk, about
+ * 4.2M elements), else COX_ERR_WORKSPACE before anything is enqueued.
+ * err_out: NULL, or a device uint32 that receives 0, or nonzero if a
+ * bounded cross-block wait of this call (or an earlier one on this device
+ * whose status was not taken) gave up; the scratch's record is then cleared.
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (other streams, other threads) race and must be serialised
+ * by the caller. */
+cox_status cox_warp_scan_noalloc(const int32_t *x, int32_t *y, int64_t n, const cox_cfg *cfg,
+                                 uint32_t *err_out, void *stream);
+
 /* Stable ballot compaction (warp votes, Sec. 2.2.1; the filtering that
  * the filter_arr kernel of Table 1 performs, here with a static full mask
  * and ballot ranks instead of its dynamic group), keeping x_i > 0:

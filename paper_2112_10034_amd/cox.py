@@ -57,6 +57,7 @@ _SIGS = {
     "cox_warp_reduce": (_I, [_P, _I, _I64, _I, C.POINTER(cox_cfg), _P, _P, _P, _SZ, _P]),
     "cox_warp_dot": (_I, [_P, _P, _I, _I64, _I, C.POINTER(cox_cfg), _P, _P, _P, _SZ, _P]),
     "cox_warp_scan": (_I, [_P, _P, _I64, C.POINTER(cox_cfg), _P, _SZ, _P]),
+    "cox_warp_scan_noalloc": (_I, [_P, _P, _I64, C.POINTER(cox_cfg), _P, _P]),
     "cox_ballot_compact": (_I, [_P, _I64, _P, _P, C.POINTER(cox_cfg), _P, _SZ, _P]),
     "cox_tile_sort": (_I, [_P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
     "cox_tile_sort_kv": (_I, [_P, _P, _P, _P, _I64, _I, C.POINTER(cox_cfg), _P]),
@@ -291,6 +292,18 @@ def warp_scan(x, cfg=None, out=None):
     ws = workspace(OP_SCAN, I32, n, cfg=cfg, device=x.device)
     _check(lib().cox_warp_scan(_ptr(x), _ptr(y), n, _cfgp(cfg), _ptr(ws.tensor), ws.nbytes, _stream()),
            "cox_warp_scan")
+    return y
+
+
+def warp_scan_noalloc(x, cfg=None, out=None, err=None):
+    """cox_warp_scan on the library's fixed device scratch (no workspace).
+    err: optional 1-element int32 device tensor receiving the wait status."""
+    _need(x, torch.int32, "x")
+    y = torch.empty_like(x) if out is None else out
+    if err is not None:
+        _need(err, torch.int32, "err")
+    _check(lib().cox_warp_scan_noalloc(_ptr(x), _ptr(y), x.numel(), _cfgp(cfg), _ptr(err), _stream()),
+           "cox_warp_scan_noalloc")
     return y
 
 

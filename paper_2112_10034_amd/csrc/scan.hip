@@ -29,6 +29,8 @@
 // have finished) resets the counter and advances the epoch whose tag marks
 // this call's status words, so the workspace needs no clearing between
 // calls.  Every wait is bounded (MAX_SPIN); running out sets HDR_ERR.
+#include <mutex>
+
 #include "cox_internal.hpp"
 
 namespace cox {
@@ -340,8 +342,8 @@ static lb_fn pick_lb(int k) {
   return nullptr;
 }
 
-static cox_status check_lookback_call(cox_op op, int64_t n, const void *x, const cox_cfg *cfg, void *ws,
-                                      size_t ws_bytes, Sigma *sg, int64_t *nch) {
+static cox_status check_lookback_args(cox_op op, int64_t n, const void *x, const cox_cfg *cfg, Sigma *sg,
+                                      int64_t *nch) {
   if (n < 0) return COX_ERR_INVALID;
   cox_status st = resolve_cfg(op, COX_I32, cfg, sg);
   if (st != COX_OK) return st;
@@ -351,7 +353,69 @@ static cox_status check_lookback_call(cox_op op, int64_t n, const void *x, const
   *nch = (n + S - 1) / S;
   // tickets and counts are 32-bit
   if (*nch > (int64_t)0x7fffffff - 65536 || n > (int64_t)0xffffffffLL) return COX_ERR_INVALID;
+  return COX_OK;
+}
+
+static cox_status check_lookback_call(cox_op op, int64_t n, const void *x, const cox_cfg *cfg, void *ws,
+                                      size_t ws_bytes, Sigma *sg, int64_t *nch) {
+  const cox_status st = check_lookback_args(op, n, x, cfg, sg, nch);
+  if (st != COX_OK) return st;
   if (!ws || ws_bytes < cox_workspace_bytes(op, COX_I32, n, 0, cfg)) return COX_ERR_WORKSPACE;
+  return COX_OK;
+}
+
+// ------------------------------------------------ allocation-free variant
+// The look-back header and status words of cox_warp_scan_noalloc live in a
+// file-scope device array.  Each device that runs the library holds its own
+// copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+constexpr size_t SCRATCH_BYTES = COX_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[MAX_DEVICES];
+
+__global__ void k_scratch_clear(uint32_t *p, int64_t words) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// hands the call's bounded-wait status to the caller and clears it
+__global__ void k_scratch_status(uint32_t *hdr, uint32_t *err_out) {
+  if (threadIdx.x == 0) {
+    *err_out = hdr[HDR_ERR];
+    hdr[HDR_ERR] = 0u;
+  }
+}
+
+// Device address of this device's scratch.  The first call on a device
+// looks it up and zeroes it on `st`, ahead of that call's kernels.
+static cox_status scratch_for_device(hipStream_t st, void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return COX_ERR_HIP;
+  }
+  if (dev < 0 || dev >= MAX_DEVICES) return COX_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+      return COX_ERR_HIP;
+    }
+    const int64_t words = (int64_t)(SCRATCH_BYTES / 4);
+    hipLaunchKernelGGL(k_scratch_clear, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, (uint32_t *)ptr,
+                       words);
+    const cox_status ls = launch_status();
+    if (ls != COX_OK) return ls;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
   return COX_OK;
 }
 
@@ -377,6 +441,36 @@ cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg 
   hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, y, (long long *)nullptr, n, nch,
                      (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
   return launch_status();
+}
+
+cox_status cox_warp_scan_noalloc(const int32_t *x, int32_t *y, int64_t n, const cox_cfg *cfg, uint32_t *err_out,
+                                 void *stream) {
+  Sigma sg;
+  int64_t nch;
+  cox_status st = check_lookback_args(COX_OP_SCAN, n, x, cfg, &sg, &nch);
+  if (st != COX_OK) return st;
+  if (cox_workspace_bytes(COX_OP_SCAN, COX_I32, n, 0, cfg) > SCRATCH_BYTES) return COX_ERR_WORKSPACE;
+  if (n > 0 && !y) return COX_ERR_INVALID;
+  if (n > 0 && !aligned16(y)) return COX_ERR_ALIGN;
+  lb_fn fn = pick_lb<MODE_SCAN>(sg.k);
+  if (!fn) return COX_ERR_UNSUPPORTED;
+  const hipStream_t hs = (hipStream_t)stream;
+  void *ws = nullptr;
+  st = scratch_for_device(hs, &ws);
+  if (st != COX_OK) return st;
+  if (n > 0) {
+    const int block = 32 * sg.W;
+    const int grid = persistent_grid((const void *)fn, block, nch, sg.G);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, hs, x, y, (long long *)nullptr, n, nch,
+                       (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
+    st = launch_status();
+    if (st != COX_OK) return st;
+  }
+  if (err_out) {
+    hipLaunchKernelGGL(k_scratch_status, dim3(1), dim3(64), 0, hs, (uint32_t *)ws, err_out);
+    st = launch_status();
+  }
+  return st;
 }
 
 cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t *count,

