@@ -1,13 +1,18 @@
-// Segmented reduce + scan + compaction over CSR segments, fused in one
-// persistent launch.
+// Segmented reduce + scan + compaction over CSR segments: two setup
+// kernels and one persistent fused kernel on one stream (one graph launch
+// in a plan).
 //
 // Segment s covers x[off[s], off[s+1]).  It is cut into chunks of
 // S = 32 * W * k elements starting at its first element (the last chunk is
-// padded), and every chunk of every segment becomes one ticket of a single
-// queue, so thousands of uneven segments share one grid.  A setup pass (one
-// block) turns the segment lengths into per-segment chunk starts, a second
-// one writes the chunk -> segment map, and empty segments get their
-// identity outputs there.
+// padded).  A segment of one chunk (1 <= len <= S, "short") needs no
+// cross-block word; several of them are packed into one block task, each
+// on as many warps as it has parts.  The block tasks and the chunks of the
+// longer segments are the work items of the persistent kernel, so
+// thousands of uneven segments share one grid.  A setup pass (one block)
+// turns the segment lengths into per-segment chunk starts and counts the
+// short segments per class, a second one writes the chunk descriptors and
+// the short-segment list, and empty segments get their identity outputs
+// there.
 //
 // Per chunk (element layout of the schedule sigma = (k, W), cox.h):
 //  - reduce partial P: lane-serial accumulation in (row, slot) order, the
@@ -46,7 +51,24 @@
 
 namespace cox {
 
-enum : int { SHDR_NC = 4 };  // header word: total chunk count (setup pass)
+// header words written by the setup pass: the number of long segments'
+// chunks, of short segments and of short-segment block tasks
+enum : int { SHDR_NCL = 5, SHDR_NS = 6, SHDR_NSB = 7 };
+// Short segments fall in NCLS <= 8 classes by their number of parts;
+// class table (ws.cls), in class order q (most parts first): [0, NCLS]
+// first segment of each class, [CLS_BLK, CLS_BLK + NCLS] first block task,
+// [CLS_R, CLS_R + NCLS) warps per segment
+constexpr int MAX_CLS = 8, CLS_BLK = 16, CLS_R = 32, CLS_WORDS = 64;
+// the setup kernels' per-block totals (long chunks, then each class)
+constexpr int SETUP_BLOCKS = 64, AGG_WORDS = 16;
+// The persistent kernel's tickets come from TICKET_LANES counters, 4 KiB
+// apart (block b draws from counter b mod Q and lane q hands out the
+// chunks q, q + Q, q + 2Q, ..): device-scope atomics on one word serialise
+// at about 15 ns each, which at S = 8192 bounded the whole launch.  The
+// counters and the lanes-finished word sit at fixed offsets after the
+// header, so that every workspace layout finds them zero.
+constexpr int TICKET_LANES = 8, LANE_WORDS = 1024;
+constexpr size_t LANE_BYTES = 4 * (size_t)LANE_WORDS * (TICKET_LANES + 1);
 
 // per-chunk descriptor: the chunk's segment and its clamped element range
 struct SegDesc {
@@ -57,9 +79,13 @@ struct SegDesc {
 
 struct SegWS {
   uint32_t *hdr;
+  uint32_t *lane;         // TICKET_LANES ticket counters, then the lanes-finished count
   uint32_t *chunk_start;  // nseg + 1
   uint32_t *done;         // nseg
-  SegDesc *desc;          // maxch
+  SegDesc *desc;          // maxch: chunks of long segments
+  SegDesc *sdesc;         // nseg: short segments, grouped by class
+  uint32_t *cls;          // CLS_WORDS: the short segments' class table
+  uint32_t *agg;          // SETUP_BLOCKS x AGG_WORDS: the setup blocks' totals
   uint64_t *w_scan;       // maxch: look-back words of int chunk sums
   uint64_t *w_cnt;        // maxch: look-back words of kept counts
   uint64_t *w_part;       // maxch: [tag | bits] reduce partials
@@ -76,6 +102,8 @@ static SegWS seg_layout(void *ws, int64_t nseg, int64_t maxch, size_t *bytes) {
   char *p = (char *)ws;
   size_t o = WS_HEADER;
   w.hdr = (uint32_t *)p;
+  w.lane = (uint32_t *)(p + o);
+  o += LANE_BYTES;
   w.chunk_start = (uint32_t *)(p + o);
   o = align8(o + 4 * (size_t)(nseg + 1));
   w.done = (uint32_t *)(p + o);
@@ -83,6 +111,12 @@ static SegWS seg_layout(void *ws, int64_t nseg, int64_t maxch, size_t *bytes) {
   o = (o + 15) & ~(size_t)15;
   w.desc = (SegDesc *)(p + o);
   o += sizeof(SegDesc) * (size_t)maxch;
+  w.sdesc = (SegDesc *)(p + o);
+  o += sizeof(SegDesc) * (size_t)nseg;
+  w.cls = (uint32_t *)(p + o);
+  o += 4 * (size_t)CLS_WORDS;
+  w.agg = (uint32_t *)(p + o);
+  o += 4 * (size_t)SETUP_BLOCKS * AGG_WORDS;
   w.w_scan = (uint64_t *)(p + o);
   o += 8 * (size_t)maxch;
   w.w_cnt = (uint64_t *)(p + o);
@@ -118,9 +152,23 @@ __device__ __forceinline__ void seg_bounds(const int64_t *off, int64_t s, int64_
 }
 
 // ---------------------------------------------------------------- setup
-// One block of 1024 threads: chunk counts ceil(len / S) scanned into
-// per-segment chunk starts (32-bit), the total written to hdr[SHDR_NC];
-// empty segments get total = identity and count = 0.
+// A short segment has r = ceil(len / 32k) parts of 32k elements (the W
+// warp parts of its chunk that hold data).  Short segments fall in
+// NCLS = min(W, 8) classes, c = (r - 1) NCLS / W, taken in the order
+// q = NCLS - 1 - c (most parts first); a segment of class c gets
+// rmax(c) = (c + 1) W / NCLS warps (its parts, then empty ones, whose
+// identity values leave every tree unchanged), and a block task takes
+// W / rmax segments of one class, so no segment spans two blocks and the
+// warps of a block have like amounts of work.
+//
+// One block of 1024 threads, thread t owning a run of consecutive
+// segments: chunk counts ceil(len / S) of the long segments scanned into
+// per-segment chunk starts (32-bit), short segments counted per class and
+// placed in their class by a scan of those counts (no atomics: device
+// atomics on a few words serialise), empty segments given total =
+// identity and count = 0; then the class table and the header words.
+// S and 32k are powers of two, so counts are shifts (64-bit divisions
+// would dominate this one-block kernel).
 //
 // Offsets that go down and up again give clamped segments that overlap,
 // and then the chunks of all segments can outnumber the workspace's
@@ -135,69 +183,282 @@ __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {  // a, b <
   return r < SEG_SAT ? r : SEG_SAT;
 }
 
-template <int DT>
-__global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
-                                                    int64_t S, uint32_t maxch, SegWS ws, void *seg_total,
-                                                    long long *seg_count) {
-  __shared__ uint32_t s_w[32];
-  __shared__ uint32_t s_carry;
-  const int t = threadIdx.x, w = t >> 5, l = t & 31;
-  if (t == 0) s_carry = 0u;
-  __syncthreads();
-  for (int64_t base = 0; base < nseg; base += 1024) {
-    const int64_t s = base + t;
-    uint32_t cnt = 0u;
-    if (s < nseg) {
-      // this call's layout of the workspace depends on its segment and
-      // chunk counts, so counters are cleared by every call, not assumed
-      ws.done[s] = 0u;
-      int64_t a, b;
-      seg_bounds(off, s, n, a, b);
-      const int64_t len = b - a;
-      const int64_t c64 = (len + S - 1) / S;
-      cnt = c64 < (int64_t)SEG_SAT ? (uint32_t)c64 : SEG_SAT;
-      if (len == 0) {
-        if (seg_total) {
-          if (DT == COX_I32) ((long long *)seg_total)[s] = 0;
-          else ((double *)seg_total)[s] = -0.0;
+// chunks of a long segment (0 for a short or empty one), saturated;
+// S = 2^shS
+__device__ __forceinline__ uint32_t seg_long_chunks(int64_t len, int64_t S, int shS) {
+  if (len <= S) return 0u;
+  const int64_t c64 = (len + S - 1) >> shS;
+  return c64 < (int64_t)SEG_SAT ? (uint32_t)c64 : SEG_SAT;
+}
+
+// class of a short segment (1 <= len <= S) with parts of 2^shRW elements
+// (W and ncls are powers of two)
+__device__ __forceinline__ int seg_class(int64_t len, int shRW, int W, int ncls) {
+  const int r = (int)((len + ((int64_t)1 << shRW) - 1) >> shRW);
+  return ((r - 1) * ncls) >> __builtin_ctz((unsigned)W);
+}
+
+// bounds of segments [base, base + SETUP_BATCH) (those below s1), their
+// offsets requested together (indices clamped to the array, so every load
+// is valid and none waits for another)
+constexpr int SETUP_BATCH = 8;
+__device__ __forceinline__ void seg_bounds_batch(const int64_t *__restrict__ off, int64_t base, int64_t s1,
+                                                 int64_t nseg, int64_t n, int64_t (&a)[SETUP_BATCH],
+                                                 int64_t (&b)[SETUP_BATCH]) {
+  int64_t o[SETUP_BATCH + 1];
+#pragma unroll
+  for (int i = 0; i <= SETUP_BATCH; i++) o[i] = off[base + i < nseg ? base + i : nseg];
+#pragma unroll
+  for (int i = 0; i < SETUP_BATCH; i++) {
+    int64_t lo = o[i], hi = o[i + 1];
+    lo = lo < 0 ? 0 : (lo > n ? n : lo);
+    hi = hi < lo ? lo : (hi > n ? n : hi);
+    a[i] = lo;
+    b[i] = base + i < s1 ? hi : lo;
+  }
+}
+
+// inclusive scan of v over the 32 lanes of the logical warp
+__device__ __forceinline__ uint32_t setup_scan32(uint32_t v) {
+  v += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)v);
+  v += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)v);
+  v += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)v);
+  v += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)v);
+  v += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)v);
+  return v;
+}
+
+// Pass-1 counts of segments [s0, s1): long chunks (saturated) and short
+// segments per class; the counting kernel also clears the segments' done
+// counters and writes the identity outputs of empty segments.
+template <int DT, bool FIRST>
+__device__ __forceinline__ void setup_counts(const int64_t *__restrict__ off, int64_t s0, int64_t s1,
+                                             int64_t nseg, int64_t n, int shS, int shRW, int W, int ncls,
+                                             SegWS ws, void *seg_total, long long *seg_count, uint32_t &cnt,
+                                             uint32_t (&cc)[MAX_CLS]) {
+  const int64_t S = (int64_t)1 << shS;
+  cnt = 0u;
+#pragma unroll
+  for (int c = 0; c < MAX_CLS; c++) cc[c] = 0u;
+  for (int64_t base = s0; base < s1; base += SETUP_BATCH) {
+    int64_t a[SETUP_BATCH], b[SETUP_BATCH];
+    seg_bounds_batch(off, base, s1, nseg, n, a, b);
+#pragma unroll
+    for (int i = 0; i < SETUP_BATCH; i++) {
+      const int64_t s = base + i;
+      if (s >= s1) break;
+      const int64_t len = b[i] - a[i];
+      cnt = sat_add(cnt, seg_long_chunks(len, S, shS));
+      if (len > 0 && len <= S) {
+        const int c = seg_class(len, shRW, W, ncls);
+#pragma unroll
+        for (int k = 0; k < MAX_CLS; k++) cc[k] += c == k ? 1u : 0u;
+      }
+      if constexpr (FIRST) {
+        // this call's layout of the workspace depends on its segment and
+        // chunk counts, so counters are cleared by every call, not assumed
+        ws.done[s] = 0u;
+        if (len == 0) {
+          if (seg_total) {
+            if (DT == COX_I32) ((long long *)seg_total)[s] = 0;
+            else ((double *)seg_total)[s] = -0.0;
+          }
+          if (seg_count) seg_count[s] = 0;
         }
-        if (seg_count) seg_count[s] = 0;
       }
     }
-    // inclusive saturating scan over the logical warp, then its exclusive
-    // form from the lane below (a saturated sum cannot be undone)
-    uint32_t v = cnt;
-    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)v));
-    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)v));
-    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)v));
-    v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)v));
-    v = sat_add(v, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)v));
-    const uint32_t vup = (uint32_t)shfl_up((int)v, 1);
-    const uint32_t vex = l == 0 ? 0u : vup;
-    if (l == 31) s_w[w] = v;
-    __syncthreads();
-    if (w == 0) {
-      uint32_t b = s_w[l];
-      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)b));
-      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)b));
-      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)b));
-      b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)b));
-      b = sat_add(b, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)b));
-      const uint32_t bup = (uint32_t)shfl_up((int)b, 1);
-      s_w[l] = l == 0 ? 0u : bup;  // exclusive over warps
-    }
-    __syncthreads();
-    const uint32_t excl = sat_add(s_carry, sat_add(s_w[w], vex));
-    if (s < nseg) ws.chunk_start[s] = excl < maxch ? excl : maxch;
-    __syncthreads();
-    if (t == 1023) s_carry = sat_add(excl, cnt);
-    __syncthreads();
   }
-  if (t == 0) {
-    const uint32_t tot = s_carry, nc = tot < maxch ? tot : maxch;
-    ws.chunk_start[nseg] = nc;
-    ws.hdr[SHDR_NC] = nc;
+}
+
+// the segments of setup block blockIdx.x owned by thread threadIdx.x
+__device__ __forceinline__ void setup_range(int64_t nseg, int64_t &s0, int64_t &s1) {
+  const int64_t pb = (nseg + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * pb < nseg ? (int64_t)blockIdx.x * pb : nseg;
+  const int64_t b1 = b0 + pb < nseg ? b0 + pb : nseg;
+  const int64_t per = (b1 - b0 + 1023) / 1024;
+  s0 = b0 + (int64_t)threadIdx.x * per < b1 ? b0 + (int64_t)threadIdx.x * per : b1;
+  s1 = s0 + per < b1 ? s0 + per : b1;
+}
+
+// Setup, first kernel: each block's totals (long chunks, short segments
+// per class) into its aggregate row.
+template <int DT>
+__global__ __launch_bounds__(1024) void k_seg_count(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
+                                                    int shS, int W, SegWS ws, void *seg_total,
+                                                    long long *seg_count) {
+  __shared__ uint32_t s_x[1 + MAX_CLS][32];
+  const int t = threadIdx.x, w = t >> 5, l = t & 31;
+  const int shW = __builtin_ctz((unsigned)W);
+  const int ncls = W < MAX_CLS ? W : MAX_CLS;
+  int64_t s0, s1;
+  setup_range(nseg, s0, s1);
+  uint32_t cnt, cc[MAX_CLS];
+  setup_counts<DT, true>(off, s0, s1, nseg, n, shS, shS - shW, W, ncls, ws, seg_total, seg_count, cnt, cc);
+  // block sums: the chunk count saturated (its lanes add with saturation)
+  uint32_t v = cnt;
+  v = sat_add(v, (uint32_t)xor_lane<16>((int)v));
+  v = sat_add(v, (uint32_t)xor_lane<8>((int)v));
+  v = sat_add(v, (uint32_t)xor_lane<4>((int)v));
+  v = sat_add(v, (uint32_t)xor_lane<2>((int)v));
+  v = sat_add(v, (uint32_t)xor_lane<1>((int)v));
+  if (l == 0) s_x[0][w] = v;
+#pragma unroll
+  for (int c = 0; c < MAX_CLS; c++) {
+    const uint32_t sc = setup_scan32(cc[c]);
+    if (l == 31) s_x[1 + c][w] = sc;
+  }
+  __syncthreads();
+  if (t < 32 * (1 + MAX_CLS) && l == 0) {
+    const int row = w;  // warp w sums row w
+    uint32_t sum = 0u;
+    for (int j = 0; j < 32; j++) sum = row == 0 ? sat_add(sum, s_x[0][j]) : sum + s_x[row][j];
+    ws.agg[(int64_t)blockIdx.x * AGG_WORDS + row] = sum;
+  }
+}
+
+// Setup, second kernel: each block's prefix from the aggregate rows of the
+// blocks before it, then the per-thread exclusive scans, the chunk starts
+// and the short segments' places (recounting its segments); block 0 writes
+// the class table and the last block the totals.
+template <int DT>
+__global__ __launch_bounds__(1024) void k_seg_setup(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
+                                                    int shS, int W, uint32_t maxch, SegWS ws) {
+  __shared__ uint32_t s_w[32];
+  __shared__ uint32_t s_cw[MAX_CLS][32];  // per class: warp sums, then their exclusive prefixes
+  __shared__ uint32_t s_bpre[1 + MAX_CLS], s_btot[1 + MAX_CLS];  // block prefix, grand total
+  const int t = threadIdx.x, w = t >> 5, l = t & 31;
+  const int shW = __builtin_ctz((unsigned)W);
+  const int ncls = W < MAX_CLS ? W : MAX_CLS;
+  const int64_t S = (int64_t)1 << shS;
+  // warp `row` (< 1 + MAX_CLS) adds column `row` of the aggregate rows
+  if (w < 1 + MAX_CLS) {
+    uint32_t pre = 0u, tot = 0u;
+    for (int j = l; j < (int)gridDim.x; j += 32) {
+      const uint32_t x = ws.agg[(int64_t)j * AGG_WORDS + w];
+      if (w == 0) {
+        tot = sat_add(tot, x);
+        if (j < (int)blockIdx.x) pre = sat_add(pre, x);
+      } else {
+        tot += x;
+        if (j < (int)blockIdx.x) pre += x;
+      }
+    }
+    for (int o = 16; o > 0; o >>= 1) {
+      const uint32_t po = (uint32_t)__shfl_xor((int)pre, o, 32), to = (uint32_t)__shfl_xor((int)tot, o, 32);
+      pre = w == 0 ? sat_add(pre, po) : pre + po;
+      tot = w == 0 ? sat_add(tot, to) : tot + to;
+    }
+    if (l == 0) {
+      s_bpre[w] = pre;
+      s_btot[w] = tot;
+    }
+  }
+  int64_t s0, s1;
+  setup_range(nseg, s0, s1);
+  uint32_t cnt, cc[MAX_CLS];
+  setup_counts<DT, false>(off, s0, s1, nseg, n, shS, shS - shW, W, ncls, ws, nullptr, nullptr, cnt, cc);
+  // exclusive saturating scan of the threads' chunk counts
+  uint32_t v = cnt;
+  v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)v));
+  v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)v));
+  v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)v));
+  v = sat_add(v, (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)v));
+  v = sat_add(v, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)v));
+  const uint32_t vup = (uint32_t)shfl_up((int)v, 1);
+  const uint32_t vex = l == 0 ? 0u : vup;
+  if (l == 31) s_w[w] = v;
+  // and of the per-class counts (a class holds at most nseg < 2^31)
+  uint32_t cinc[MAX_CLS];
+#pragma unroll
+  for (int c = 0; c < MAX_CLS; c++) {
+    cinc[c] = setup_scan32(cc[c]);
+    if (l == 31) s_cw[c][w] = cinc[c];
+  }
+  __syncthreads();
+  if (w == 0) {
+    uint32_t b = s_w[l];
+    b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)b));
+    b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)b));
+    b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)b));
+    b = sat_add(b, (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)b));
+    b = sat_add(b, (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)b));
+    const uint32_t bup = (uint32_t)shfl_up((int)b, 1);
+    s_w[l] = sat_add(s_bpre[0], l == 0 ? 0u : bup);  // exclusive over warps, after the blocks before
+#pragma unroll
+    for (int c = 0; c < MAX_CLS; c++) {
+      const uint32_t x = s_cw[c][l];
+      const uint32_t xi = setup_scan32(x);
+      s_cw[c][l] = s_bpre[1 + c] + xi - x;
+    }
+  }
+  __syncthreads();
+  // class starts in the order q = ncls - 1 - c (most parts first)
+  uint32_t cstart[MAX_CLS];
+  {
+    uint32_t acc = 0u;
+#pragma unroll
+    for (int q = 0; q < MAX_CLS; q++) {
+      const int c = ncls - 1 - q;
+      if (c >= 0) {
+        cstart[c] = acc;
+        acc += s_btot[1 + c];
+      }
+    }
+  }
+  // this thread's first place in each class
+  uint32_t cpos[MAX_CLS];
+#pragma unroll
+  for (int c = 0; c < MAX_CLS; c++) cpos[c] = c < ncls ? cstart[c] + s_cw[c][w] + (cinc[c] - cc[c]) : 0u;
+  uint32_t excl = sat_add(s_w[w], vex);
+  for (int64_t base = s0; base < s1; base += SETUP_BATCH) {
+    int64_t a[SETUP_BATCH], b[SETUP_BATCH];
+    seg_bounds_batch(off, base, s1, nseg, n, a, b);
+#pragma unroll
+    for (int i = 0; i < SETUP_BATCH; i++) {
+      const int64_t s = base + i;
+      if (s >= s1) break;
+      ws.chunk_start[s] = excl < maxch ? excl : maxch;
+      const int64_t len = b[i] - a[i];
+      excl = sat_add(excl, seg_long_chunks(len, S, shS));
+      if (len > 0 && len <= S) {
+        const int c = seg_class(len, shS - shW, W, ncls);
+        uint32_t pos = 0u;
+#pragma unroll
+        for (int k = 0; k < MAX_CLS; k++)
+          if (c == k) pos = cpos[k]++;
+        SegDesc d;
+        d.a = a[i];
+        d.b = b[i];
+        d.s = (uint32_t)s;
+        d.lo = 0u;
+        d.nchs = 1u;
+        d.pad = 0u;
+        if ((int64_t)pos < nseg) ws.sdesc[pos] = d;
+      }
+    }
+  }
+  if (blockIdx.x == gridDim.x - 1 && t == 0) {
+    const uint32_t tot = s_btot[0], ncl = tot < maxch ? tot : maxch;
+    ws.chunk_start[nseg] = ncl;
+    ws.hdr[SHDR_NCL] = ncl;
     if (tot > maxch) st_dev32(&ws.hdr[HDR_ERR], ERR_LAYOUT);
+  }
+  if (blockIdx.x == 0 && t == 0) {
+    // class table in the order q
+    uint32_t ns = 0u, nb = 0u;
+    for (int q = 0; q < ncls; q++) {
+      const int c = ncls - 1 - q;
+      const uint32_t rmax = (uint32_t)((c + 1) * W / ncls), spb = (uint32_t)W / rmax;
+      ws.cls[q] = ns;
+      ws.cls[CLS_BLK + q] = nb;
+      ws.cls[CLS_R + q] = rmax;
+      ns += s_btot[1 + c];
+      nb += (s_btot[1 + c] + spb - 1u) / spb;
+    }
+    ws.cls[ncls] = ns;
+    ws.cls[CLS_BLK + ncls] = nb;
+    ws.hdr[SHDR_NS] = ns;
+    ws.hdr[SHDR_NSB] = nb;
   }
 }
 
@@ -206,25 +467,46 @@ __global__ __launch_bounds__(256) void k_seg_clear(uint32_t *p, int64_t words) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256) p[i] = 0u;
 }
 
-// one logical warp per segment: the descriptors of its chunks
+// One thread per segment (grid-stride, a whole wave per step); the long
+// segments' chunk descriptors are written by the whole wave, one segment
+// at a time, its 64 lanes over the chunks.
 __global__ __launch_bounds__(256) void k_seg_map(const int64_t *__restrict__ off, int64_t nseg, int64_t n,
-                                                 SegWS ws) {
-  const int64_t wg = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 5;
-  const int64_t nw = ((int64_t)gridDim.x * 256) >> 5;
-  const int l = threadIdx.x & 31;
-  for (int64_t s = wg; s < nseg; s += nw) {
-    const uint32_t c0 = ws.chunk_start[s], c1 = ws.chunk_start[s + 1];
+                                                 int64_t S, SegWS ws) {
+  for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s - (int64_t)__lane_id() < nseg;
+       s += (int64_t)gridDim.x * 256) {
+  SegDesc d;
+  d.a = d.b = 0;
+  d.s = (uint32_t)s;
+  d.lo = 0u;
+  d.nchs = 0u;
+  d.pad = 0u;
+  bool is_long = false;
+  if (s < nseg) {
     int64_t a, b;
     seg_bounds(off, s, n, a, b);
-    SegDesc d;
-    d.a = a;
-    d.b = b;
-    d.s = (uint32_t)s;
-    d.lo = c0;
-    d.nchs = c1 - c0;
-    d.pad = 0u;
-    for (uint32_t c = c0 + l; c < c1; c += 32) {
-      ws.desc[c] = d;
+    if (b - a > S) {
+      d.a = a;
+      d.b = b;
+      d.lo = ws.chunk_start[s];
+      d.nchs = ws.chunk_start[s + 1] - d.lo;
+      is_long = true;
+    }
+  }
+  const int lane = (int)__lane_id();
+  uint64_t longs = __builtin_amdgcn_ballot_w64(is_long);
+  while (longs) {
+    const int ld = __builtin_ctzll(longs);
+    SegDesc e;
+    e.a = ((int64_t)__builtin_amdgcn_readlane((int)(d.a >> 32), ld) << 32) |
+          (uint32_t)__builtin_amdgcn_readlane((int)d.a, ld);
+    e.b = ((int64_t)__builtin_amdgcn_readlane((int)(d.b >> 32), ld) << 32) |
+          (uint32_t)__builtin_amdgcn_readlane((int)d.b, ld);
+    e.s = (uint32_t)__builtin_amdgcn_readlane((int)d.s, ld);
+    e.lo = (uint32_t)__builtin_amdgcn_readlane((int)d.lo, ld);
+    e.nchs = (uint32_t)__builtin_amdgcn_readlane((int)d.nchs, ld);
+    e.pad = 0u;
+    for (uint32_t c = e.lo + (uint32_t)lane; c < e.lo + e.nchs; c += 64) {
+      ws.desc[c] = e;
       // the chunk's cross-block words start with tag 0 (no call's tag):
       // this memory may hold another layout's words from an earlier call
       ws.w_scan[c] = 0;
@@ -234,6 +516,8 @@ __global__ __launch_bounds__(256) void k_seg_map(const int64_t *__restrict__ off
       ws.w_ph[c] = 0;
       ws.w_pl[c] = 0;
     }
+    longs &= longs - 1;
+  }
   }
 }
 
@@ -463,16 +747,99 @@ __device__ long long seg_sum_i64(const uint64_t *p, int64_t a, int64_t b, uint32
 typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint32_t u32x2u __attribute__((ext_vector_type(2), aligned(4)));
 
+// the row vectors of a warp part starting at wbase, in a range that ends
+// at e1 <= n: one 16-byte load per row vector, the identity past e1.  The
+// loads are unconditional, each into its own registers, so that they are
+// all in flight together (conditional loads into registers that other
+// lanes set to the identity made the compiler wait for each one); a row
+// wholly past e1 reads x[0..3] instead (one line for all such lanes).  The
+// one vector that would reach past the end of x is read element by element
+// afterwards.  x of fewer than four elements is read element by element.
+template <int R, int V, int DT>
+__device__ __forceinline__ void seg_load_part(const uint32_t *__restrict__ x, int64_t n, int64_t wbase,
+                                              int64_t e1, uint32_t (&v)[R][V]) {
+  const int l = llane();
+  constexpr uint32_t I = SegT<DT>::ident;
+  if constexpr (V == 4) {
+    if (n >= 4) {
+      const int64_t e0 = wbase + (int64_t)l * 4;
+      u32x4u q[R];
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        const int64_t e = e0 + i * 128;
+        q[i] = __builtin_nontemporal_load((const u32x4u *)(x + (e < e1 && e + 4 <= n ? e : 0)));
+      }
+#pragma unroll
+      for (int i = 0; i < R; i++) {
+        const int64_t e = e0 + i * 128;
+        v[i][0] = e < e1 ? q[i].x : I;
+        v[i][1] = e + 1 < e1 ? q[i].y : I;
+        v[i][2] = e + 2 < e1 ? q[i].z : I;
+        v[i][3] = e + 3 < e1 ? q[i].w : I;
+      }
+      if (e1 + 4 > n) {
+#pragma unroll
+        for (int i = 0; i < R; i++) {
+          const int64_t e = e0 + i * 128;
+          if (e < e1 && e + 4 > n)
+#pragma unroll
+            for (int j = 0; j < 4; j++) v[i][j] = e + j < e1 ? x[e + j] : I;
+        }
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; i++) {
+    const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+#pragma unroll
+    for (int j = 0; j < V; j++) v[i][j] = e + j < e1 ? ld_stream1(x + e + j) : I;
+  }
+}
+
+// stores of a warp part's row vectors inside a range that ends at e1
+template <int R, int V>
+__device__ __forceinline__ void seg_store_part(uint32_t *__restrict__ y, int64_t wbase, int64_t e1,
+                                               const uint32_t (&o)[R][V]) {
+  const int l = llane();
+#pragma unroll
+  for (int i = 0; i < R; i++) {
+    const int64_t e = wbase + (int64_t)(i * 32 + l) * V;
+    bool done = false;
+    if constexpr (V == 4) {
+      if (e + 4 <= e1) {
+        // plain stores: L2 joins the lanes' unaligned vectors into lines
+        const u32x4u q = {o[i][0], o[i][1], o[i][2], o[i][3]};
+        *(u32x4u *)(y + e) = q;
+        done = true;
+      }
+    }
+    if (!done) {
+#pragma unroll
+      for (int j = 0; j < V; j++)
+        if (e + j < e1) y[e + j] = o[i][j];
+    }
+  }
+}
+
+__device__ __forceinline__ void seg_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- fused kernel
-// Per block: draw a ticket and resolve it, with one dependent load, into
-// one of two shared descriptor slots; for each chunk: (1) one thread of the
-// block's last wave draws and resolves the next ticket while the block
-// loads the chunk and does its row work (reduce partials, compaction ranks
-// staged in the warp's LDS region, scan rows); (2) role warps on different
-// waves combine the warp values, publish them and run their look-backs --
-// scan on warp 0, compaction on warp 2, reduce total on warp 4 (folded onto
-// warp 0 in small blocks); a segment of one chunk needs no cross-block
-// word at all; (3) outputs.
+// Per block, for each work item: (1) one thread of the block's last wave
+// draws a ticket from the block's lane and resolves it, with one dependent
+// load, into the shared slot; (2) every warp loads its part (a long
+// chunk's warp w: the chunk's 32k elements from 32kw on; a short task's
+// warp: part v of its own segment) and does its row work (reduce partial,
+// compaction ranks staged in the warp's LDS region, scan rows); (3) roles:
+// for a long chunk, role warps on different waves combine the warp values,
+// publish them and run their look-backs -- scan on warp 0, compaction on
+// warp 2, reduce total on warp 4 (folded onto warp 0 in small blocks); for
+// a short task, each segment's first warp combines its warps' values;
+// (4) outputs.
 template <int K, int DT>
 __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__ x, const int64_t *__restrict__ off,
                                                     int64_t nseg, int64_t n, int64_t nc_arg, uint32_t maxch,
@@ -482,7 +849,8 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   constexpr int R = K / V;
   using T = SegT<DT>;
   __shared__ uint32_t s_epoch;
-  __shared__ uint32_t s_tk[2], s_seg[2], s_lo[2], s_nchs[2];
+  __shared__ uint32_t s_tk[2], s_seg[2], s_lo[2], s_nchs[2], s_kind[2];
+  __shared__ uint32_t s_cls[3 * (MAX_CLS + 1)];  // the class table: segments, block tasks, warps
   __shared__ int64_t s_e0[2], s_e1[2], s_ob[2];
   __shared__ uint32_t s_wred[32], s_wscan[32], s_wcnt[32], s_E[32], s_coff[32];
   __shared__ uint32_t s_last[3];
@@ -497,15 +865,40 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   const int64_t S = (int64_t)blockDim.x * K;
   const uint32_t lt = lanemask_lt();
   const bool single = nc_arg >= 0;
-  // the setup pass clamps the chunk count to the workspace's capacity;
-  // the bound is repeated here so that no ticket can index past it
-  const uint32_t nc_ws = ld_dev32(&ws.hdr[SHDR_NC]);
-  const int64_t NC = single ? nc_arg : (int64_t)(nc_ws < maxch ? nc_ws : maxch);
+  // work items u: [0, NSB) the block tasks of short segments, then
+  // [NSB, NSB + NC) the long segments' chunks in order.  The setup pass
+  // clamps the chunk count to the workspace's capacity; the bounds are
+  // repeated here so that no ticket can index past them.
+  int64_t NC = nc_arg, NSB = 0;
+  if (!single) {
+    const uint32_t ncl = ld_dev32(&ws.hdr[SHDR_NCL]), nsb = ld_dev32(&ws.hdr[SHDR_NSB]);
+    NC = ncl < maxch ? ncl : maxch;
+    NSB = (int64_t)nsb < nseg ? (int64_t)nsb : nseg;
+    const int t = threadIdx.x;
+    if (t < MAX_CLS + 1) s_cls[t] = ws.cls[t];
+    else if (t < 2 * (MAX_CLS + 1)) s_cls[t] = ws.cls[CLS_BLK + t - (MAX_CLS + 1)];
+    else if (t < 3 * (MAX_CLS + 1)) s_cls[t] = ws.cls[CLS_R + t - 2 * (MAX_CLS + 1)];
+  }
+  const int64_t NU = NSB + NC;
+  // ticket lane q of Q: its blocks draw tickets t = 0, 1, .. for items
+  // tQ + q; tickets [NUq, NUq + Gq) are its blocks' exit tickets.  The
+  // smallest unfinished item is always drawn or about to be (its lane's
+  // earlier items are all finished, so that lane's blocks are free), and
+  // the first Q blocks, dispatched first, keep every lane served.
+  const int64_t G = gridDim.x;
+  const int64_t Q = G < TICKET_LANES ? G : TICKET_LANES;
+  const int64_t q = (int64_t)blockIdx.x % Q;
+  const int64_t Gq = (G - q + Q - 1) / Q;
+  const int64_t NUq = NU > q ? (NU - q + Q - 1) / Q : 0;
+  uint32_t *const lane_ctr = ws.lane + q * LANE_WORDS;
 
-  // thread tD: ticket t's chunk into slot
+  // thread tD: ticket t's item into slot
   auto resolve = [&](uint32_t t, int slot) {
     s_tk[slot] = t;
-    if ((int64_t)t < NC) {
+    const int64_t u = (int64_t)t * Q + q;
+    s_kind[slot] = u < NSB ? 1u : 0u;
+    if ((int64_t)t < NUq && u >= NSB) {
+      const int64_t ch = u - NSB;
       int64_t a, b, s, lo, nchs;
       if (single) {
         seg_bounds(off, 0, n, a, b);
@@ -513,7 +906,7 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
         lo = 0;
         nchs = nc_arg;
       } else {
-        const SegDesc d = ws.desc[t];
+        const SegDesc d = ws.desc[ch];
         a = d.a;
         b = d.b;
         s = d.s;
@@ -524,14 +917,15 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
       s_lo[slot] = (uint32_t)lo;
       s_nchs[slot] = (uint32_t)nchs;
       s_ob[slot] = a;
-      s_e0[slot] = a + ((int64_t)t - lo) * S;
+      s_e0[slot] = a + (ch - lo) * S;
       s_e1[slot] = b;
     }
   };
-  // the chunk's vectors (padding with the identity past the segment)
-  auto load = [&](int64_t e0, int64_t e1, uint32_t (&v)[R][V]) {
+  // the warp's vectors (padding with the identity past the segment); a
+  // short task's warps each start at their own part (e0 + 32Kw)
+  auto load = [&](int64_t e0, int64_t e1, bool full, uint32_t (&v)[R][V]) {
     const int64_t wbase = e0 + (int64_t)w * 32 * K;
-    if (e0 + S <= e1) {
+    if (full) {
       const uint32_t *src = x + wbase + l * V;
 #pragma unroll
       for (int i = 0; i < R; i++) {
@@ -547,13 +941,7 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
         }
       }
     } else {
-#pragma unroll
-      for (int i = 0; i < R; i++)
-#pragma unroll
-        for (int j = 0; j < V; j++) {
-          const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-          v[i][j] = e < e1 ? ld_stream1(x + e) : T::ident;
-        }
+      seg_load_part<R, V, DT>(x, n, wbase, e1, v);
     }
   };
 
@@ -563,23 +951,54 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   const uint32_t tag = tag_of_epoch(epoch);
   const int slot = 0;
 
-  int64_t c;
+  int64_t tk;
   for (;;) {
     // a ticket is drawn only when the block can start on it at once: a
     // drawn chunk that waited for the block's previous one would hold up
     // the look-backs of the chunks after it
-    if (threadIdx.x == tD) resolve(add_dev32(&ws.hdr[HDR_TICKET], 1u), 0);
+    if (threadIdx.x == tD) resolve(add_dev32(lane_ctr, 1u), 0);
     __syncthreads();
-    c = s_tk[0];
-    if (c >= NC) break;
-    // the slot is read here only: the next ticket overwrites it while slow
-    // threads may still be writing this chunk's outputs
-    const int64_t s = s_seg[slot], lo = s_lo[slot], e0 = s_e0[slot], e1 = s_e1[slot], ob = s_ob[slot];
-    const uint32_t nchs = s_nchs[slot];
-    const bool full = e0 + S <= e1;
+    tk = s_tk[0];
+    if (tk >= NUq) break;
+    const int64_t u = tk * Q + q;  // the item
+    const bool shortk = s_kind[slot] != 0u;
+    // long chunk: c, its segment s, the segment's first chunk lo and its
+    // chunk count nchs, the chunk's range [e0, e1), the segment's start ob.
+    // (The slot is read here only: the next ticket overwrites it while
+    // slow threads may still be writing this item's outputs.)
+    const int64_t c = u - NSB;
+    int64_t s = s_seg[slot], lo = s_lo[slot], e0 = s_e0[slot], e1 = s_e1[slot], ob = s_ob[slot];
+    uint32_t nchs = s_nchs[slot];
+    // short task: warp w holds part v of segment j of class cq (r parts),
+    // segment range [ob, e1) (an absent segment: the empty range)
+    int v = 0, rp = 1;
+    bool has = true;
+    if (shortk) {
+      const int ncls = W < MAX_CLS ? W : MAX_CLS;
+      const uint32_t *seg0 = s_cls, *blk0 = s_cls + MAX_CLS + 1, *rmx = s_cls + 2 * (MAX_CLS + 1);
+      int cq = 0;
+      while (cq + 1 < ncls && blk0[cq + 1] <= (uint32_t)u) cq++;
+      rp = (int)rmx[cq];
+      const int spb = W / rp, j = w / rp;
+      v = w - j * rp;
+      const uint32_t j0 = ((uint32_t)u - blk0[cq]) * (uint32_t)spb, nq = seg0[cq + 1] - seg0[cq];
+      has = j < spb && j0 + (uint32_t)j < nq && (int64_t)(seg0[cq] + j0 + j) < nseg;
+      ob = e1 = 0;
+      s = 0;
+      if (has) {
+        const SegDesc d = ws.sdesc[seg0[cq] + j0 + j];
+        ob = d.a;
+        e1 = d.b;
+        s = d.s;
+      }
+      e0 = ob + (int64_t)v * 32 * K - (int64_t)w * 32 * K;  // so that e0 + 32Kw is the part's start
+      lo = 0;
+      nchs = 1;
+    }
+    const bool full = !shortk && e0 + S <= e1;
     const int64_t wbase = e0 + (int64_t)w * 32 * K;
     uint32_t xr[R][V];
-    load(e0, e1, xr);
+    load(e0, e1, full, xr);
 
     // ---- reduce partial: lane-serial then the warp tree
     if (flags & SF_REDUCE) {
@@ -639,6 +1058,37 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
     const bool one = nchs == 1;  // the segment is this chunk alone
 
     // ---- roles
+    if (shortk) {
+      // the segment's first warp combines its rp warps' values
+      if (has && v == 0) {
+        if (flags & SF_REDUCE) {
+          uint32_t bt = l < rp ? s_wred[w + l] : T::ident;
+          bt = seg_tree<DT>(bt);
+          if (l == 0) {
+            if constexpr (DT == COX_I32) ((long long *)seg_total)[s] = (long long)(int32_t)bt;
+            else ((double *)seg_total)[s] = -0.0 + (double)i2f((int)bt);
+          }
+        }
+        if (flags & SF_SCAN) {
+          uint32_t at = l < rp ? s_wscan[w + l] : T::ident;
+          uint32_t ex;
+          seg_scan32<DT>(at, ex);
+          if (l < rp) s_E[w + l] = ex;
+        }
+        if (flags & SF_COMPACT) {
+          const uint32_t cc = l < rp ? s_wcnt[w + l] : 0u;
+          uint32_t incl = cc;
+          incl += (uint32_t)dpp<DPP_ROW_SHR1>(0, (int)incl);
+          incl += (uint32_t)dpp<DPP_ROW_SHR2>(0, (int)incl);
+          incl += (uint32_t)dpp<DPP_ROW_SHR4>(0, (int)incl);
+          incl += (uint32_t)dpp<DPP_ROW_SHR8>(0, (int)incl);
+          incl += (uint32_t)dpp<DPP_ROW_BCAST15, 0xa>(0, (int)incl);
+          if (l < rp) s_coff[w + l] = incl - cc;
+          const uint32_t tot = (uint32_t)bcast31((int)incl);
+          if (l == 0 && seg_count) seg_count[s] = (long long)tot;
+        }
+      }
+    } else {
     if ((flags & SF_REDUCE) && w == wR) {
       uint32_t b = l < W ? s_wred[l] : T::ident;
       b = seg_tree<DT>(b);
@@ -705,14 +1155,18 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
         if (seg_count && c == lo + nchs - 1) seg_count[s] = (long long)pre + (long long)agg;
       }
     }
+    }
     __syncthreads();
 
     // ---- outputs
     if (flags & SF_SCAN) {
-      const uint32_t E = w == 0 ? T::ident : s_E[w];
+      // a short segment's parts and a long chunk's warps take E_v / E_w
+      // (the first one the identity) and the segment's carry (none in a
+      // one-chunk segment: 0, or -0.0 in FP64)
+      const uint32_t E = (shortk ? v : w) == 0 ? T::ident : s_E[w];
       uint32_t o[R][V];
       if constexpr (DT == COX_I32) {
-        const uint32_t pre = s_pre_i;
+        const uint32_t pre = shortk ? 0u : s_pre_i;
 #pragma unroll
         for (int i = 0; i < R; i++) {
           const uint32_t base = T::add(T::add(E, cin[i]), exv[i]);
@@ -720,7 +1174,7 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
           for (int j = 0; j < V; j++) o[i][j] = pre + T::add(base, xr[i][j]);
         }
       } else {
-        const double pre = s_pre_f;
+        const double pre = shortk ? -0.0 : s_pre_f;
 #pragma unroll
         for (int i = 0; i < R; i++) {
           const uint32_t base = T::add(T::add(E, cin[i]), exv[i]);
@@ -745,20 +1199,14 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
             *(u32x4u *)(dst + i * 32 * V) = q;
           }
         }
-      } else {
-#pragma unroll
-        for (int i = 0; i < R; i++)
-#pragma unroll
-          for (int j = 0; j < V; j++) {
-            const int64_t e = wbase + (int64_t)(i * 32 + l) * V + j;
-            if (e < e1) y[e] = o[i][j];
-          }
+      } else if (has) {
+        seg_store_part<R, V>(y, wbase, e1, o);
       }
     }
-    if (flags & SF_COMPACT) {
+    if ((flags & SF_COMPACT) && has) {
       const uint32_t *region = s_stage + w * 32 * K;
       const uint32_t wcnt = s_wcnt[w];
-      const int64_t obase = ob + (int64_t)s_pre_c + s_coff[w];
+      const int64_t obase = ob + (shortk ? (int64_t)0 : (int64_t)s_pre_c) + s_coff[w];
       for (uint32_t q = l; q < wcnt; q += 32) {
         const int64_t pos = obase + q;
         if (pos < e1) outc[pos] = region[q];  // bound: guards a failed wait only
@@ -766,18 +1214,23 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
     }
   }
 
-  if (threadIdx.x == tD && c == NC + (int64_t)gridDim.x - 1) {
-    // last exit ticket (every block has drawn its last one)
-    if (nc_arg == 0) {
-      // single-segment launch of an empty segment: identity outputs
-      if ((flags & SF_REDUCE) && seg_total) {
-        if (DT == COX_I32) ((long long *)seg_total)[0] = 0;
-        else ((double *)seg_total)[0] = -0.0;
+  if (threadIdx.x == tD && tk == NUq + Gq - 1) {
+    // the lane's last exit ticket (all its blocks have drawn their last
+    // one); the lane finishing last has every block's last ticket behind it
+    st_dev32(lane_ctr, 0u);
+    uint32_t *const finished = ws.lane + TICKET_LANES * LANE_WORDS;
+    if (add_dev32(finished, 1u) == (uint32_t)(Q - 1)) {
+      if (nc_arg == 0) {
+        // single-segment launch of an empty segment: identity outputs
+        if ((flags & SF_REDUCE) && seg_total) {
+          if (DT == COX_I32) ((long long *)seg_total)[0] = 0;
+          else ((double *)seg_total)[0] = -0.0;
+        }
+        if ((flags & SF_COMPACT) && seg_count) seg_count[0] = 0;
       }
-      if ((flags & SF_COMPACT) && seg_count) seg_count[0] = 0;
+      st_dev32(finished, 0u);
+      st_dev32(&ws.hdr[HDR_EPOCH], epoch + 1u);
     }
-    st_dev32(&ws.hdr[HDR_TICKET], 0u);
-    st_dev32(&ws.hdr[HDR_EPOCH], epoch + 1u);
   }
 }
 
@@ -861,28 +1314,37 @@ static cox_status seg_prepare(const void *x, cox_dtype dt, const int64_t *offset
   sc->fn = fn;
   sc->lds = lds;
   sc->maxch = (uint32_t)maxch;
-  // default: as many blocks as fit, capped by the chunk bound
-  sc->grid = persistent_grid((const void *)fn, block, maxch, sg.G, lds);
+  // default: as many blocks as fit, capped by the work items
+  sc->grid = persistent_grid((const void *)fn, block, maxch + nseg, sg.G, lds);
   return COX_OK;
 }
 
 static cox_status seg_launch(const SegCall &sc, hipStream_t st) {
   const int block = 32 * sc.sg.W;
   const int64_t S = (int64_t)block * sc.sg.k;
+  const int shS = __builtin_ctzll((unsigned long long)S);  // S is a power of two
   if (sc.nseg == 0) return COX_OK;
-  if (sc.dt == COX_I32)
-    hipLaunchKernelGGL(k_seg_setup<COX_I32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.maxch, sc.ws,
-                       (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr,
-                       (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr);
-  else
-    hipLaunchKernelGGL(k_seg_setup<COX_F32>, dim3(1), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, S, sc.maxch, sc.ws,
-                       (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr,
-                       (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr);
+  // setup blocks: about 2048 segments each, at most SETUP_BLOCKS
+  int64_t sb = (sc.nseg + 2047) / 2048;
+  if (sb > SETUP_BLOCKS) sb = SETUP_BLOCKS;
+  void *tot = (sc.flags & SF_REDUCE) ? sc.seg_total : nullptr;
+  long long *cnt = (sc.flags & SF_COMPACT) ? (long long *)sc.seg_count : nullptr;
+  if (sc.dt == COX_I32) {
+    hipLaunchKernelGGL(k_seg_count<COX_I32>, dim3((unsigned)sb), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, shS,
+                       sc.sg.W, sc.ws, tot, cnt);
+    hipLaunchKernelGGL(k_seg_setup<COX_I32>, dim3((unsigned)sb), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, shS,
+                       sc.sg.W, sc.maxch, sc.ws);
+  } else {
+    hipLaunchKernelGGL(k_seg_count<COX_F32>, dim3((unsigned)sb), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, shS,
+                       sc.sg.W, sc.ws, tot, cnt);
+    hipLaunchKernelGGL(k_seg_setup<COX_F32>, dim3((unsigned)sb), dim3(1024), 0, st, sc.off, sc.nseg, sc.n, shS,
+                       sc.sg.W, sc.maxch, sc.ws);
+  }
   cox_status r = launch_status();
   if (r != COX_OK) return r;
-  int mg = (int)((sc.nseg * 32 + 255) / 256);
+  int mg = (int)((sc.nseg + 255) / 256);
   if (mg > 4096) mg = 4096;
-  hipLaunchKernelGGL(k_seg_map, dim3(mg), dim3(256), 0, st, sc.off, sc.nseg, sc.n, sc.ws);
+  hipLaunchKernelGGL(k_seg_map, dim3(mg), dim3(256), 0, st, sc.off, sc.nseg, sc.n, S, sc.ws);
   r = launch_status();
   if (r != COX_OK) return r;
   hipLaunchKernelGGL(sc.fn, dim3(sc.grid), dim3(block), sc.lds, st, (const uint32_t *)sc.x, sc.off, sc.nseg, sc.n,

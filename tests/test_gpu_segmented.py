@@ -8,7 +8,7 @@ from paper_2112_10034_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-SIGMAS = [(1, 1), (4, 8), (8, 4), (16, 8), (2, 16), (8, 16), (16, 4), (32, 8), (32, 2)]
+SIGMAS = [(1, 1), (4, 8), (8, 4), (16, 8), (2, 16), (8, 16), (16, 4), (32, 8), (32, 2), (32, 16)]
 
 
 @pytest.fixture(scope="module")
@@ -53,6 +53,44 @@ def test_segmented_fused_bit_exact(dev, oracle_mod, dtype, k, W):
     print("segmented", dtype, k, W, flush=True)
     got = cox.segmented(torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda(), 7, cfg=(k, W))
     check(torch, got, oracle_mod.segmented(x, off, k, W), off.size - 1)
+
+
+def short_mix(k, W, seed):
+    """Segments of one chunk or less at every round count (1 .. W parts of
+    32k elements), the round boundaries (32k, 32k + 1), one element, a
+    whole chunk, a chunk plus one, empty segments, and a few long ones,
+    shuffled so that warps of one wave and one block get unlike lengths."""
+    S, RW = 32 * W * k, 32 * k
+    rng = np.random.default_rng(seed)
+    lens = [1, 2, 3, RW - 1, RW, RW + 1, S - 1, S, S + 1, 2 * S + 5, 0, 0]
+    lens += [int(r * RW - rng.integers(0, RW)) for r in range(1, W + 1) for _ in range(5)]
+    lens += [int(v) for v in rng.integers(1, S + 1, size=150)]
+    lens = np.array(lens, np.int64)
+    rng.shuffle(lens)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    xi, xf = inputs.segment_values(int(off[-1]), seed=seed)
+    return off, xi, xf
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
+@pytest.mark.parametrize("k,W", [(4, 8), (32, 8), (8, 4), (4, 1), (1, 2), (2, 16), (16, 32)])
+def test_short_segments_by_one_warp(dev, oracle_mod, dtype, k, W):
+    """Segments no longer than a chunk run on one logical warp each, their
+    parts one after another; every output must still be the oracle's."""
+    torch, cox = dev
+    off, xi, xf = short_mix(k, W, 31 + k + W)
+    x = xi if dtype == "i32" else xf
+    print("short segments", dtype, k, W, "nseg", off.size - 1, "n", off[-1], flush=True)
+    xg, og = torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda()
+    want = oracle_mod.segmented(x, off, k, W)
+    check(torch, cox.segmented(xg, og, 7, cfg=(k, W)), want, off.size - 1)
+    # single outputs take the same path
+    t, _, _, _ = cox.segmented(xg, og, cox.SEG_REDUCE, cfg=(k, W))
+    assert np.array_equal(bits(t.cpu().numpy()), bits(want[0]))
+    _, y, _, _ = cox.segmented(xg, og, cox.SEG_SCAN, cfg=(k, W))
+    assert np.array_equal(bits(y.cpu().numpy()), bits(want[1]))
+    _, _, oc, cnt = cox.segmented(xg, og, cox.SEG_COMPACT, cfg=(k, W))
+    assert np.array_equal(cnt.cpu().numpy(), want[3]) and np.array_equal(bits(oc.cpu().numpy()), bits(want[2]))
 
 
 @pytest.mark.parametrize("dtype", ["i32", "f32"])
