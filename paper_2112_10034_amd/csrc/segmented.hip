@@ -952,11 +952,8 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
   const int slot = 0;
 
   int64_t tk;
+  if (threadIdx.x == tD) resolve(add_dev32(lane_ctr, 1u), 0);
   for (;;) {
-    // a ticket is drawn only when the block can start on it at once: a
-    // drawn chunk that waited for the block's previous one would hold up
-    // the look-backs of the chunks after it
-    if (threadIdx.x == tD) resolve(add_dev32(lane_ctr, 1u), 0);
     __syncthreads();
     tk = s_tk[0];
     if (tk >= NUq) break;
@@ -1157,6 +1154,13 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
     }
     }
     __syncthreads();
+    // the next ticket, drawn once this item's cross-block work is done and
+    // resolved after its outputs are issued: the item it names waits only
+    // for those stores.  (Drawing at the start of an item reserved chunks
+    // for a whole item, and every later chunk of their segment waited in
+    // its look-back for them: 1.5-4x slower.)
+    uint32_t next_t = 0u;
+    if (threadIdx.x == tD) next_t = add_dev32(lane_ctr, 1u);
 
     // ---- outputs
     if (flags & SF_SCAN) {
@@ -1204,14 +1208,31 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
       }
     }
     if ((flags & SF_COMPACT) && has) {
+      // the warp's kept run [obase, obase + wcnt) from its region, in
+      // 16-byte vectors aligned in global memory: lane j takes positions
+      // [A + 4j, A + 4j + 4) of each 128-position step, A = obase rounded
+      // down to a multiple of 4; the run's partial first and last vectors
+      // element by element (positions relative to A)
       const uint32_t *region = s_stage + w * 32 * K;
       const uint32_t wcnt = s_wcnt[w];
       const int64_t obase = ob + (shortk ? (int64_t)0 : (int64_t)s_pre_c) + s_coff[w];
-      for (uint32_t q = l; q < wcnt; q += 32) {
-        const int64_t pos = obase + q;
-        if (pos < e1) outc[pos] = region[q];  // bound: guards a failed wait only
+      const int64_t A = obase & ~(int64_t)3;
+      const uint32_t head = (uint32_t)(obase - A);
+      int64_t span = (int64_t)head + wcnt;
+      if (A + span > e1) span = e1 > A ? e1 - A : 0;  // the bound guards a failed wait only
+      uint32_t *dst = outc + A;
+      for (uint32_t t = 4u * (uint32_t)l; (int64_t)t < span; t += 128u) {
+        if (t >= head && (int64_t)t + 4 <= span) {
+          const u32x4u v = *(const u32x4u *)(region + (t - head));
+          *(u32x4u *)(dst + t) = v;
+        } else {
+#pragma unroll
+          for (uint32_t j = 0; j < 4u; j++)
+            if (t + j >= head && (int64_t)(t + j) < span) dst[t + j] = region[t + j - head];
+        }
       }
     }
+    if (threadIdx.x == tD) resolve(next_t, 0);
   }
 
   if (threadIdx.x == tD && tk == NUq + Gq - 1) {
