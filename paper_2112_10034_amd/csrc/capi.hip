@@ -226,7 +226,7 @@ size_t cox_workspace_bytes(cox_op op, cox_dtype dtype, int64_t n, int64_t nseg, 
   case COX_OP_REDUCE:
   case COX_OP_DOT: return WS_HEADER + 16 * (size_t)(nch + 1);  // up to two tagged words per chunk
   case COX_OP_SCAN:
-  case COX_OP_COMPACT: return WS_HEADER + 8 * (size_t)(nch + 1);
+  case COX_OP_COMPACT: return WS_HEADER + 8 * ST_STRIDE * (size_t)(nch + 1);
   case COX_OP_SEGMENTED: {
     // chunks of every segment (each segment rounds up)
     if (nseg < 0) return 0;

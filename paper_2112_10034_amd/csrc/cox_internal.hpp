@@ -18,7 +18,12 @@ constexpr size_t WS_HEADER = 256;
 // exceed the workspace's capacity
 constexpr uint32_t ERR_LAYOUT = 0x80000000u;
 
-// look-back status word: [tag:30][flag:2][value:32]
+// look-back status word: [tag:30][flag:2][value:32].  In a workspace the
+// words of consecutive chunks sit ST_STRIDE words (128 bytes) apart, one
+// per cache line: device-scope polls of one chunk's word and stores of its
+// neighbours' then no longer meet on a line (scan 0.372 -> 0.356 ms,
+// compaction 0.344 -> 0.325 ms at 2^28).
+constexpr int ST_STRIDE = 16;
 enum : uint32_t { ST_AGG = 1, ST_PREFIX = 2 };
 constexpr uint32_t TAG_MOD = (1u << 30) - 1;
 __host__ __device__ __forceinline__ uint32_t tag_of_epoch(uint32_t e) { return 1u + e % TAG_MOD; }

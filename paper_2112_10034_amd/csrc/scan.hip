@@ -65,19 +65,19 @@ __device__ __forceinline__ uint32_t warp_sum_u32(uint32_t v) {
 // finds an inclusive prefix, and publishes the chunk's inclusive prefix.
 // Returns the exclusive prefix (same in every lane).
 __device__ __forceinline__ uint64_t lookback_begin(int64_t c, uint32_t agg, uint64_t *__restrict__ status,
-                                                   uint32_t tag) {
+                                                   int64_t sst, uint32_t tag) {
   const int l = llane();
   if (c == 0) {
     if (l == 0) st_dev(&status[0], st_pack(tag, ST_PREFIX, agg));
     return 0;
   }
-  if (l == 0) st_dev(&status[c], st_pack(tag, ST_AGG, agg));
+  if (l == 0) st_dev(&status[c * sst], st_pack(tag, ST_AGG, agg));
   const int64_t idx = c - 1 - l;
-  return idx >= 0 ? ld_dev(&status[idx]) : st_pack(tag, ST_PREFIX, 0u);
+  return idx >= 0 ? ld_dev(&status[idx * sst]) : st_pack(tag, ST_PREFIX, 0u);
 }
 
 __device__ uint32_t lookback_end(int64_t c, uint32_t agg, uint64_t first, uint64_t *__restrict__ status,
-                                 uint32_t tag, uint32_t *__restrict__ hdr) {
+                                 int64_t sst, uint32_t tag, uint32_t *__restrict__ hdr) {
   const int l = llane();
   if (c == 0) return 0u;
   uint32_t run = 0u;
@@ -93,7 +93,7 @@ __device__ uint32_t lookback_end(int64_t c, uint32_t agg, uint64_t first, uint64
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        s = ld_dev(&status[idx]);
+        s = ld_dev(&status[idx * sst]);
       }
     }
     const uint32_t flag = st_flag(s), val = st_val(s);
@@ -105,9 +105,9 @@ __device__ uint32_t lookback_end(int64_t c, uint32_t agg, uint64_t first, uint64
     }
     run += warp_sum_u32(val);
     top -= 32;
-    s = top - l >= 0 ? ld_dev(&status[top - l]) : st_pack(tag, ST_PREFIX, 0u);
+    s = top - l >= 0 ? ld_dev(&status[(top - l) * sst]) : st_pack(tag, ST_PREFIX, 0u);
   }
-  if (l == 0) st_dev(&status[c], st_pack(tag, ST_PREFIX, agg + run));
+  if (l == 0) st_dev(&status[c * sst], st_pack(tag, ST_PREFIX, agg + run));
   return run;
 }
 
@@ -132,7 +132,8 @@ enum { MODE_SCAN = 0, MODE_COMPACT = 1 };
 template <int K, int MODE>
 __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x, int32_t *__restrict__ out,
                                                    long long *__restrict__ count, int64_t n, int64_t nch,
-                                                   uint64_t *__restrict__ status, uint32_t *__restrict__ hdr) {
+                                                   uint64_t *__restrict__ status, int64_t sst,
+                                                   uint32_t *__restrict__ hdr) {
   constexpr int V = K < 4 ? K : 4;
   constexpr int R = K / V;
   __shared__ uint32_t s_epoch, s_tk[2];
@@ -242,13 +243,13 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
       wa = l < W ? s_w[l] : 0u;
       wincl = warp_incl_scan_u32(wa);
       agg = (uint32_t)bcast31((int)wincl);
-      first = lookback_begin(c, agg, status, tag);
+      first = lookback_begin(c, agg, status, sst, tag);
     }
     __builtin_amdgcn_sched_barrier(0);
     if (full) load_full(cn, nxt, cn >= nfull);
     __builtin_amdgcn_sched_barrier(0);
     if (w == 0) {
-      const uint32_t pre = lookback_end(c, agg, first, status, tag, hdr);
+      const uint32_t pre = lookback_end(c, agg, first, status, sst, tag, hdr);
       if (l < W) s_w[l] = pre + (wincl - wa);
       if constexpr (MODE == MODE_COMPACT)
         if (c == nch - 1 && l == 0) *count = (long long)pre + (long long)agg;
@@ -327,7 +328,8 @@ __global__ __launch_bounds__(1024) void k_lookback(const int32_t *__restrict__ x
   }
 }
 
-using lb_fn = void (*)(const int32_t *, int32_t *, long long *, int64_t, int64_t, uint64_t *, uint32_t *);
+using lb_fn = void (*)(const int32_t *, int32_t *, long long *, int64_t, int64_t, uint64_t *, int64_t,
+                       uint32_t *);
 
 template <int MODE>
 static lb_fn pick_lb(int k) {
@@ -439,7 +441,7 @@ cox_status cox_warp_scan(const int32_t *x, int32_t *y, int64_t n, const cox_cfg 
   const int block = 32 * sg.W;
   const int grid = persistent_grid((const void *)fn, block, nch, sg.G);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, (hipStream_t)stream, x, y, (long long *)nullptr, n, nch,
-                     (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
+                     (uint64_t *)((char *)ws + WS_HEADER), (int64_t)ST_STRIDE, (uint32_t *)ws);
   return launch_status();
 }
 
@@ -449,7 +451,9 @@ cox_status cox_warp_scan_noalloc(const int32_t *x, int32_t *y, int64_t n, const 
   int64_t nch;
   cox_status st = check_lookback_args(COX_OP_SCAN, n, x, cfg, &sg, &nch);
   if (st != COX_OK) return st;
-  if (cox_workspace_bytes(COX_OP_SCAN, COX_I32, n, 0, cfg) > SCRATCH_BYTES) return COX_ERR_WORKSPACE;
+  // status words packed 8 bytes apart (a workspace spaces them ST_STRIDE
+  // words apart), so that 1 MiB covers every n the default schedule takes
+  if (WS_HEADER + 8 * (size_t)(nch + 1) > SCRATCH_BYTES) return COX_ERR_WORKSPACE;
   if (n > 0 && !y) return COX_ERR_INVALID;
   if (n > 0 && !aligned16(y)) return COX_ERR_ALIGN;
   lb_fn fn = pick_lb<MODE_SCAN>(sg.k);
@@ -462,7 +466,7 @@ cox_status cox_warp_scan_noalloc(const int32_t *x, int32_t *y, int64_t n, const 
     const int block = 32 * sg.W;
     const int grid = persistent_grid((const void *)fn, block, nch, sg.G);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(block), 0, hs, x, y, (long long *)nullptr, n, nch,
-                       (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
+                       (uint64_t *)((char *)ws + WS_HEADER), (int64_t)1, (uint32_t *)ws);
     st = launch_status();
     if (st != COX_OK) return st;
   }
@@ -490,7 +494,7 @@ cox_status cox_ballot_compact(const int32_t *x, int64_t n, int32_t *out, int64_t
     return COX_ERR_UNSUPPORTED;
   const int grid = persistent_grid((const void *)fn, block, nch > 0 ? nch : 1, sg.G, lds);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds - 256, (hipStream_t)stream, x, out, (long long *)count, n,
-                     nch, (uint64_t *)((char *)ws + WS_HEADER), (uint32_t *)ws);
+                     nch, (uint64_t *)((char *)ws + WS_HEADER), (int64_t)ST_STRIDE, (uint32_t *)ws);
   return launch_status();
 }
 

@@ -86,13 +86,17 @@ struct SegWS {
   SegDesc *sdesc;         // nseg: short segments, grouped by class
   uint32_t *cls;          // CLS_WORDS: the short segments' class table
   uint32_t *agg;          // SETUP_BLOCKS x AGG_WORDS: the setup blocks' totals
-  uint64_t *w_scan;       // maxch: look-back words of int chunk sums
-  uint64_t *w_cnt;        // maxch: look-back words of kept counts
-  uint64_t *w_part;       // maxch: [tag | bits] reduce partials
-  uint64_t *w_tot;        // maxch: [tag | bits] float chunk scan totals
-  uint64_t *w_ph;         // maxch: [tag | high half] FP64 inclusive prefixes
-  uint64_t *w_pl;         // maxch: [tag | low half]
+  // a chunk's cross-block words, word c * CW of each array: one 128-byte
+  // record per chunk, so that chunks never share a cache line
+  uint64_t *w_scan;       // look-back words of int chunk sums
+  uint64_t *w_cnt;        // look-back words of kept counts
+  uint64_t *w_part;       // [tag | bits] reduce partials
+  uint64_t *w_tot;        // [tag | bits] float chunk scan totals
+  uint64_t *w_ph;         // [tag | high half] FP64 inclusive prefixes
+  uint64_t *w_pl;         // [tag | low half]
 };
+// words from one chunk's record to the next's
+constexpr int64_t CW = 16;
 
 static size_t align8(size_t v) { return (v + 7) & ~(size_t)7; }
 
@@ -117,18 +121,15 @@ static SegWS seg_layout(void *ws, int64_t nseg, int64_t maxch, size_t *bytes) {
   o += 4 * (size_t)CLS_WORDS;
   w.agg = (uint32_t *)(p + o);
   o += 4 * (size_t)SETUP_BLOCKS * AGG_WORDS;
-  w.w_scan = (uint64_t *)(p + o);
-  o += 8 * (size_t)maxch;
-  w.w_cnt = (uint64_t *)(p + o);
-  o += 8 * (size_t)maxch;
-  w.w_part = (uint64_t *)(p + o);
-  o += 8 * (size_t)maxch;
-  w.w_tot = (uint64_t *)(p + o);
-  o += 8 * (size_t)maxch;
-  w.w_ph = (uint64_t *)(p + o);
-  o += 8 * (size_t)maxch;
-  w.w_pl = (uint64_t *)(p + o);
-  o += 8 * (size_t)maxch;
+  o = (o + 127) & ~(size_t)127;
+  uint64_t *rec = (uint64_t *)(p + o);
+  w.w_scan = rec;
+  w.w_cnt = rec + 1;
+  w.w_part = rec + 2;
+  w.w_tot = rec + 3;
+  w.w_ph = rec + 4;
+  w.w_pl = rec + 5;
+  o += 8 * (size_t)CW * (size_t)maxch;
   if (bytes) *bytes = o;
   return w;
 }
@@ -509,12 +510,12 @@ __global__ __launch_bounds__(256) void k_seg_map(const int64_t *__restrict__ off
       ws.desc[c] = e;
       // the chunk's cross-block words start with tag 0 (no call's tag):
       // this memory may hold another layout's words from an earlier call
-      ws.w_scan[c] = 0;
-      ws.w_cnt[c] = 0;
-      ws.w_part[c] = 0;
-      ws.w_tot[c] = 0;
-      ws.w_ph[c] = 0;
-      ws.w_pl[c] = 0;
+      ws.w_scan[c * CW] = 0;
+      ws.w_cnt[c * CW] = 0;
+      ws.w_part[c * CW] = 0;
+      ws.w_tot[c * CW] = 0;
+      ws.w_ph[c * CW] = 0;
+      ws.w_pl[c * CW] = 0;
     }
     longs &= longs - 1;
   }
@@ -574,12 +575,12 @@ __device__ __forceinline__ uint64_t seg_lb_begin(int64_t c, int64_t lo, uint32_t
                                                  uint32_t tag) {
   const int l = llane();
   if (c == lo) {
-    if (l == 0) st_dev(&st[c], st_pack(tag, ST_PREFIX, agg));
+    if (l == 0) st_dev(&st[c * CW], st_pack(tag, ST_PREFIX, agg));
     return 0;
   }
-  if (l == 0) st_dev(&st[c], st_pack(tag, ST_AGG, agg));
+  if (l == 0) st_dev(&st[c * CW], st_pack(tag, ST_AGG, agg));
   const int64_t idx = c - 1 - l;
-  return idx >= lo ? ld_dev(&st[idx]) : st_pack(tag, ST_PREFIX, 0u);
+  return idx >= lo ? ld_dev(&st[idx * CW]) : st_pack(tag, ST_PREFIX, 0u);
 }
 
 __device__ __forceinline__ uint32_t seg_wsum(uint32_t v) {
@@ -608,7 +609,7 @@ __device__ uint32_t seg_lb_end(int64_t c, int64_t lo, uint32_t agg, uint64_t fir
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        s = ld_dev(&st[idx]);
+        s = ld_dev(&st[idx * CW]);
       }
     }
     const uint32_t pm = ballot(st_flag(s) == ST_PREFIX);
@@ -619,15 +620,16 @@ __device__ uint32_t seg_lb_end(int64_t c, int64_t lo, uint32_t agg, uint64_t fir
     }
     run += seg_wsum(st_val(s));
     top -= 32;
-    s = top - l >= lo ? ld_dev(&st[top - l]) : st_pack(tag, ST_PREFIX, 0u);
+    s = top - l >= lo ? ld_dev(&st[(top - l) * CW]) : st_pack(tag, ST_PREFIX, 0u);
   }
-  if (l == 0) st_dev(&st[c], st_pack(tag, ST_PREFIX, agg + run));
+  if (l == 0) st_dev(&st[c * CW], st_pack(tag, ST_PREFIX, agg + run));
   return run;
 }
 
-// value bits of tagged word p[i] (bounded wait for the call's tag)
+// chunk i's tagged word of array p (records CW words apart; bounded wait
+// for the call's tag)
 __device__ __forceinline__ uint64_t seg_word(const uint64_t *p, int64_t i, uint32_t tag, uint32_t *hdr) {
-  uint64_t s = ld_dev(&p[i]);
+  uint64_t s = ld_dev(&p[i * CW]);
   uint32_t spins = 0;
   while ((uint32_t)(s >> 32) != tag) {
     if (++spins >= MAX_SPIN || ((spins & 1023u) == 0u && ld_dev32(&hdr[HDR_ERR]) == tag)) {
@@ -635,7 +637,7 @@ __device__ __forceinline__ uint64_t seg_word(const uint64_t *p, int64_t i, uint3
       break;
     }
     __builtin_amdgcn_s_sleep(1);
-    s = ld_dev(&p[i]);
+    s = ld_dev(&p[i * CW]);
   }
   return s;
 }
@@ -671,9 +673,9 @@ __device__ __forceinline__ F64Win seg_f64_begin(int64_t c, int64_t lo, const Seg
   F64Win r = {0, 0, 0};
   const int64_t idx = c - 1 - llane();
   if (c > lo && idx >= lo) {
-    r.h = ld_dev(&ws.w_ph[idx]);
-    r.lw = ld_dev(&ws.w_pl[idx]);
-    r.t = ld_dev(&ws.w_tot[idx]);
+    r.h = ld_dev(&ws.w_ph[idx * CW]);
+    r.lw = ld_dev(&ws.w_pl[idx * CW]);
+    r.t = ld_dev(&ws.w_tot[idx * CW]);
   }
   return r;
 }
@@ -701,7 +703,7 @@ __device__ double seg_f64_end(int64_t c, int64_t lo, uint32_t tc, F64Win win, co
               break;
             }
             __builtin_amdgcn_s_sleep(1);
-            win.t = ld_dev(&ws.w_tot[idx]);
+            win.t = ld_dev(&ws.w_tot[idx * CW]);
           }
           tv = i2f((int)(uint32_t)win.t);
         }
@@ -720,15 +722,15 @@ __device__ double seg_f64_end(int64_t c, int64_t lo, uint32_t tc, F64Win win, co
       }
       __builtin_amdgcn_s_sleep(1);
       if (idx >= lo) {
-        win.h = ld_dev(&ws.w_ph[idx]);
-        win.lw = ld_dev(&ws.w_pl[idx]);
+        win.h = ld_dev(&ws.w_ph[idx * CW]);
+        win.lw = ld_dev(&ws.w_pl[idx * CW]);
       }
     }
   }
   const double pc = carry + (double)i2f((int)tc);
   if (l == 0) {
-    st_dev(&ws.w_ph[c], ((uint64_t)tag << 32) | (uint32_t)__double2hiint(pc));
-    st_dev(&ws.w_pl[c], ((uint64_t)tag << 32) | (uint32_t)__double2loint(pc));
+    st_dev(&ws.w_ph[c * CW], ((uint64_t)tag << 32) | (uint32_t)__double2hiint(pc));
+    st_dev(&ws.w_pl[c * CW], ((uint64_t)tag << 32) | (uint32_t)__double2loint(pc));
   }
   return carry;
 }
@@ -1097,7 +1099,7 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
       } else {
         uint32_t d = 0u;
         if (l == 0) {
-          st_dev(&ws.w_part[c], ((uint64_t)tag << 32) | b);
+          st_dev(&ws.w_part[c * CW], ((uint64_t)tag << 32) | b);
           d = add_dev32(&ws.done[s], 1u);
         }
         // the chunk completing the segment's count adds its partials
@@ -1129,7 +1131,7 @@ __global__ __launch_bounds__(1024) void k_segmented(const uint32_t *__restrict__
           // q at the chunk's last slot: ((E_{W-1} + C) + ex) + z
           const uint32_t ew = (uint32_t)shfl((int)ex, W - 1);
           const uint32_t tc = T::add(T::add(T::add(ew, s_last[0]), s_last[1]), s_last[2]);
-          if (l == 0) st_dev(&ws.w_tot[c], ((uint64_t)tag << 32) | tc);
+          if (l == 0) st_dev(&ws.w_tot[c * CW], ((uint64_t)tag << 32) | tc);
           pre = seg_f64_end(c, lo, tc, seg_f64_begin(c, lo, ws), ws, tag);
         }
         if (l == 0) s_pre_f = pre;

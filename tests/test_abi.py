@@ -54,7 +54,9 @@ def test_host_only_queries(cox):
     assert k in (1, 2, 4, 8, 16, 32) and W in (1, 2, 4, 8, 16, 32) and G == 0
     n = 1 << 20
     S = 32 * W * k
-    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n, 0, None) == 256 + 8 * (-(-n // S) + 1)
+    # status words one per 128-byte line
+    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n, 0, None) == 256 + 128 * (-(-n // S) + 1)
+    assert L.cox_workspace_bytes(cox.OP_COMPACT, cox.I32, n, 0, None) == 256 + 128 * (-(-n // S) + 1)
     assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, -1, 0, None) == 0
     bad = cox.make_cfg(3, 8)
     assert L.cox_workspace_bytes(cox.OP_REDUCE, cox.F32, n, 0, C.byref(bad)) == 0
@@ -193,7 +195,7 @@ def test_noalloc_scan_rejects_sizes_beyond_its_scratch(cox):
     fake = C.c_void_p(1 << 12)  # never dereferenced: every check below fails on the host
     small = cox.make_cfg(1, 1)  # 32 elements per chunk
     n_over = ((cap - 256) // 8) * 32  # one chunk more than the scratch holds
-    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n_over, 0, C.byref(small)) > cap
+    assert 256 + 8 * (n_over // 32 + 1) > cap >= 256 + 8 * (n_over // 32)  # packed 8-byte status words
     assert L.cox_warp_scan_noalloc(fake, fake, n_over, C.byref(small), None, None) == 5
     assert L.cox_warp_scan_noalloc(fake, fake, -1, None, None, None) == 1
     assert L.cox_warp_scan_noalloc(None, fake, 64, None, None, None) == 1

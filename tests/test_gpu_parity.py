@@ -200,6 +200,39 @@ def test_scan_compaction_edge_sizes_and_reuse(dev, oracle_mod):
         ws.status()
 
 
+def test_compaction_many_chunks_and_reuse(dev):
+    """Many small chunks (look-backs over several status windows), inputs
+    shorter than one chunk, empty inputs, and schedules alternating on one
+    workspace (every call leaves the ticket counter and the epoch ready for
+    the next)."""
+    torch, cox = dev
+    for cfg, n in (((1, 1), 200_000), ((1, 2), 64 * 1000 + 17), ((32, 16), 16384 * 9 + 4000), ((32, 16), 5000),
+                   ((32, 16), 0), ((32, 32), 3 * 32768 + 7), ((2, 16), 1024 * 300 + 1), ((32, 32), 0),
+                   ((32, 16), 16384 * 40), ((4, 8), 1)):
+        say("compact case", cfg, n)
+        x, _, _ = inputs.primitive_inputs(n)
+        out, cnt = cox.ballot_compact(up(torch, x), cfg=cfg)
+        c = int(down(cnt)[0])
+        assert c == int((x > 0).sum()), (cfg, n)
+        assert np.array_equal(down(out)[:c], x[x > 0]), (cfg, n)
+    for ws in cox._ws_cache.values():
+        ws.status()
+
+
+def test_compaction_grid_sizes(dev):
+    """Grids of one block, of a few blocks, and of more blocks than chunks."""
+    torch, cox = dev
+    x, _, _ = inputs.primitive_inputs(16384 * 23 + 99)
+    want = x[x > 0]
+    for G in (1, 3, 8, 13, 300):
+        say("compact grid", G)
+        out, cnt = cox.ballot_compact(up(torch, x), cfg=(32, 16, G))
+        c = int(down(cnt)[0])
+        assert c == want.size and np.array_equal(down(out)[:c], want), G
+    for ws in cox._ws_cache.values():
+        ws.status()
+
+
 def test_scan_of_ones_and_determinism(dev):
     torch, cox = dev
     n = 1_000_003

