@@ -94,6 +94,24 @@ def test_short_segments_by_one_warp(dev, oracle_mod, dtype, k, W):
 
 
 @pytest.mark.parametrize("dtype", ["i32", "f32"])
+@pytest.mark.parametrize("nseg", [16384, 16385, 40000])
+def test_many_segments(dev, oracle_mod, dtype, nseg):
+    """Eight and nine setup blocks (2048 segments each) and twenty, with
+    empty, short and a few long segments."""
+    torch, cox = dev
+    rng = np.random.default_rng(nseg)
+    lens = rng.integers(0, 400, size=nseg)
+    lens[rng.integers(0, nseg, size=20)] = rng.integers(5000, 40000, size=20)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    xi, xf = inputs.segment_values(int(off[-1]), seed=nseg)
+    x = xi if dtype == "i32" else xf
+    print("many segments", dtype, "nseg", nseg, "n", off[-1], flush=True)
+    xg, og = torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda()
+    want = oracle_mod.segmented(x, off, 4, 8)
+    check(torch, cox.segmented(xg, og, 7, cfg=(4, 8)), want, nseg)
+
+
+@pytest.mark.parametrize("dtype", ["i32", "f32"])
 def test_segmented_single_outputs_match_fused(dev, oracle_mod, dtype):
     torch, cox = dev
     off, xi, xf = small_case()
