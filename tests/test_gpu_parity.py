@@ -219,6 +219,26 @@ def test_compaction_many_chunks_and_reuse(dev):
         ws.status()
 
 
+@pytest.mark.parametrize("k,W", [(32, 8), (4, 4), (8, 4), (16, 16), (32, 32), (2, 8)])
+def test_scan_and_compaction_few_blocks(dev, k, W):
+    """Grids of one, two and five blocks, so that every block takes many
+    chunks in turn, each chunk's rows requested during the previous one."""
+    torch, cox = dev
+    S = 32 * W * k
+    x, _, _ = inputs.primitive_inputs(S * 21 + 77)
+    want_y = np.cumsum(x.astype(np.int64)).astype(np.int32)
+    want_c = x[x > 0]
+    for G in (1, 2, 5):
+        say("scan/compaction few blocks", k, W, G)
+        y = down(cox.warp_scan(up(torch, x), cfg=(k, W, G)))
+        assert np.array_equal(y, want_y), G
+        out, cnt = cox.ballot_compact(up(torch, x), cfg=(k, W, G))
+        c = int(down(cnt)[0])
+        assert c == want_c.size and np.array_equal(down(out)[:c], want_c), G
+    for ws in cox._ws_cache.values():
+        ws.status()
+
+
 def test_compaction_grid_sizes(dev):
     """Grids of one block, of a few blocks, and of more blocks than chunks."""
     torch, cox = dev
