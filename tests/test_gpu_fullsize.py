@@ -87,6 +87,32 @@ def test_full_compaction(dev, oracle_mod, prim):
     cox.workspace(cox.OP_COMPACT, cox.I32, N).status()
 
 
+def test_scan_and_compaction_past_2p31(dev):
+    """n = 2^31 + 4099 (element indices past the int32 range, a ragged last
+    chunk) at the default schedules: the int32 sum against numpy's int64
+    sum, the scan against its definition, the prefix sum wrapping mod 2^32
+    (numpy's cumsum in uint32), and the compaction against numpy's
+    selection of x > 0, element by element."""
+    torch, cox = dev
+    n = (1 << 31) + 4099
+    print("sum, scan and compaction at n =", n, flush=True)
+    x = inputs.masked_input(n, seed=77)
+    xg = up(torch, x)
+    t, _ = cox.warp_reduce(xg, partials=False)
+    assert int(down(t).reshape(-1)[0]) == int(x.sum(dtype=np.int64))
+    y = down(cox.warp_scan(xg))
+    want = np.cumsum(x.view(np.uint32), dtype=np.uint32).view(np.int32)
+    assert np.array_equal(y, want)
+    del y, want
+    out, cnt = cox.ballot_compact(xg)
+    keep = x[x > 0]
+    c = int(down(cnt)[0])
+    assert c == keep.size
+    assert np.array_equal(down(out[:c]), keep)
+    for op in (cox.OP_REDUCE, cox.OP_SCAN, cox.OP_COMPACT):
+        cox.workspace(op, cox.I32, n).status()
+
+
 def test_full_tile_sort(dev, oracle_mod, prim):
     torch, cox = dev
     keys = prim[1]
