@@ -367,3 +367,30 @@ def test_per_segment_launches_captured_in_a_graph(dev, oracle_mod):
         torch.cuda.synchronize()
         check(torch, (tot, y, oc, cnt), want, nseg)
         assert torch.isfinite(junk)
+
+
+def test_segments_past_2p31_elements(dev):
+    """2^31 + 4099 int32 elements in segments of 2^30 + 3 and 2^30 + 14
+    elements, an empty one, a short one and a ragged last one, at the
+    default schedule: totals against numpy's int64 sums, the scan against
+    its definition (each segment's prefix sum wrapping mod 2^32) and each
+    segment's kept run (at the segment's own offset) against numpy's
+    selection of x > 0."""
+    torch, cox = dev
+    n = (1 << 31) + 4099
+    off = np.array([0, (1 << 30) + 3, (1 << 31) + 17, (1 << 31) + 17, (1 << 31) + 4000, n], np.int64)
+    print("segments past 2^31 elements, n =", n, flush=True)
+    x = inputs.masked_input(n, seed=78)
+    xg, og = torch.from_numpy(x).cuda(), torch.from_numpy(off).cuda()
+    tot, y, oc, cnt = cox.segmented(xg, og, 7)
+    tot, cnt = tot.cpu().numpy(), cnt.cpu().numpy()
+    y = y.cpu().numpy()
+    for s in range(off.size - 1):
+        a, b = int(off[s]), int(off[s + 1])
+        seg = x[a:b]
+        assert int(tot[s]) == int(seg.sum(dtype=np.int64)), s
+        assert np.array_equal(y[a:b], np.cumsum(seg.view(np.uint32), dtype=np.uint32).view(np.int32)), s
+        keep = seg[seg > 0]
+        assert int(cnt[s]) == keep.size, s
+        assert np.array_equal(oc[a:a + keep.size].cpu().numpy(), keep), s
+    cox.workspace(cox.OP_SEGMENTED, cox.I32, n, off.size - 1).status()
