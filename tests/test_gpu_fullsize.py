@@ -113,6 +113,21 @@ def test_scan_and_compaction_past_2p31(dev):
         cox.workspace(op, cox.I32, n).status()
 
 
+def test_tile_sort_past_2p31(dev):
+    """2^31 + 32 * 7 + 19 keys (a ragged last group, padded with the
+    maximum key inside the kernel and never written back) at the
+    benchmark's schedule: each 32-key group against numpy's sort."""
+    torch, cox = dev
+    n = (1 << 31) + 32 * 7 + 19
+    print("tile sort at n =", n, flush=True)
+    keys = inputs.masked_input(n, seed=79)
+    got = down(cox.tile_sort(up(torch, keys), cfg=(4, 0))).view(np.uint32)
+    k = keys.view(np.uint32)
+    m = n // 32 * 32
+    assert np.array_equal(got[:m].reshape(-1, 32), np.sort(k[:m].reshape(-1, 32), axis=1))
+    assert np.array_equal(got[m:], np.sort(k[m:]))
+
+
 def test_full_tile_sort(dev, oracle_mod, prim):
     torch, cox = dev
     keys = prim[1]
