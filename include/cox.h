@@ -155,6 +155,20 @@ cox_status cox_warp_shfl(const int32_t *v, int32_t *out, int64_t n, int op, int3
 cox_status cox_warp_vote(const int32_t *pred, const uint32_t *mask, int64_t n, uint32_t *ballot,
                          int32_t *anyall, void *stream);
 
+/* Tile-scoped votes of cooperative groups' thread_block_tile<T> (the
+ * static groups of Sec. 2.2.2 with the votes of Sec. 2.2.1): every warp
+ * (n % 32 == 0) is 32/T tiles of T consecutive lanes, T in {1, 2, 4, 8,
+ * 16, 32}, each a whole group.  For tile g (elements gT .. gT + T - 1):
+ *     ballot[g] = sum over i < T of (pred[gT + i] != 0) << i   (T bits)
+ *     anyall[g] = tile.any(pred) | tile.all(pred) << 1
+ * written by the tile's rank-0 lane.  A lane's thread_rank() in its tile
+ * is e mod T, and its tile's rank among the tiles of its warp is
+ * (e mod 32) / T (meta_group_rank() of a partition of a 32-thread tile).
+ * pred: int32[n]; ballot: uint32[n / T]; anyall: int32[n / T]; device
+ * buffers. */
+cox_status cox_tile_vote(const int32_t *pred, int64_t n, int tile, uint32_t *ballot, int32_t *anyall,
+                         void *stream);
+
 /* ---------------------------------------------------------------------
  * Block reduction with warp shuffles (Sec. 2.3 Code 1 generalised to a
  * 256-thread block, the SDK reduction kernels of Table 1).

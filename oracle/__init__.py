@@ -56,6 +56,7 @@ def lib():
             "coxo_counts": (I, [P, I]),
             "coxo_warp_shfl": (I, [P, P, I64, I, C.c_int32, P, I, P]),
             "coxo_warp_vote": (I, [P, P, I64, P, P]),
+            "coxo_tile_vote": (I, [P, I64, I, P, P]),
             "coxo_reduce_blocks_i32": (I, [P, I64, P, P]),
             "coxo_reduce": (I, [P, I, I64, I, I, I, P, P]),
             "coxo_dot": (I, [P, P, I, I64, I, I, I, P, P]),
@@ -149,6 +150,16 @@ def warp_vote(pred, mask=None):
     aa = np.zeros(g, np.int32)
     m = None if mask is None else _c(mask, np.uint32)
     _check(lib().coxo_warp_vote(_p(pred), _p(m), pred.size, _p(bal), _p(aa)), "warp_vote")
+    return bal, aa
+
+
+def tile_vote(pred, T):
+    """Per tile of T lanes: (T-bit ballot, any | all << 1)."""
+    pred = _c(pred, np.int32)
+    g = pred.size // T if T > 0 else 0
+    bal = np.zeros(g, np.uint32)
+    aa = np.zeros(g, np.int32)
+    _check(lib().coxo_tile_vote(_p(pred), pred.size, int(T), _p(bal), _p(aa)), "tile_vote")
     return bal, aa
 
 

@@ -415,6 +415,57 @@ int coxo_warp_vote(const int32_t *pred, const uint32_t *mask, int64_t n, uint32_
   return run_blocks(n / 32, vote_block, &c);
 }
 
+/* Tile-scoped votes of cooperative groups' thread_block_tile<T> (the
+ * static groups of Sec. 2.2.2, with the votes of Sec. 2.2.1): a warp is
+ * 32/T tiles of T consecutive lanes, each a whole group (no mask).  Every
+ * lane supplies its predicate to the warp's exchange array; lane l of the
+ * tile that starts at lane b reads the tile's T entries: tile.ballot has
+ * bit i set iff lane b + i's predicate is nonzero, tile.any() is true iff
+ * one is, tile.all() iff all T are.  The tile's rank-0 lane stores
+ * ballot[tile] and anyall[tile] = any | all << 1. */
+typedef struct {
+  const int32_t *pred;
+  int T;
+  uint32_t *ballot;
+  int32_t *anyall;
+} tvote_ctx;
+
+static uint32_t wf_tile_ballot(const xch_t *x, int l, int T) {
+  const uint32_t tile = (T == 32 ? 0xFFFFFFFFu : ((1u << T) - 1u)) << (l - l % T);
+  if (!call_ok(x, l, tile)) return 0;
+  uint32_t r = 0;
+  for (int i = 0; i < T; i++)
+    if (x->v[l - l % T + i] != 0) r |= 1u << i;
+  return r;
+}
+
+static void tvote_block(void *p, int64_t g) {
+  tvote_ctx *c = (tvote_ctx *)p;
+  const int T = c->T;
+  const uint32_t full = T == 32 ? 0xFFFFFFFFu : (1u << T) - 1u;
+  xch_t X;
+  xch_war(&X);
+  uint32_t b[32];
+  int a[32], al[32];
+  for (int l = 0; l < 32; l++) xch_put(&X, l, c->pred[32 * g + l] != 0);
+  for (int l = 0; l < 32; l++) {
+    b[l] = wf_tile_ballot(&X, l, T);
+    a[l] = b[l] != 0;
+    al[l] = b[l] == full;
+  }
+  xch_war(&X);
+  for (int l = 0; l < 32; l += T) {
+    c->ballot[(32 * g + l) / T] = b[l];
+    c->anyall[(32 * g + l) / T] = a[l] | (al[l] << 1);
+  }
+}
+
+int coxo_tile_vote(const int32_t *pred, int64_t n, int T, uint32_t *ballot, int32_t *anyall) {
+  if (n < 0 || n % 32 || T < 1 || T > 32 || (T & (T - 1))) return COXO_ERR_INVALID;
+  tvote_ctx c = {pred, T, ballot, anyall};
+  return run_blocks(n / 32, tvote_block, &c);
+}
+
 /* ================================================================== */
 /* K-R0: 256-thread blocks (8 warps), one element per thread:          */
 /*   shfl_down tree (offsets 16..1) per warp, ballot(x > 0) per warp,  */

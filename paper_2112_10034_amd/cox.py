@@ -53,6 +53,7 @@ _SIGS = {
     "cox_workspace_status": (_I, [_P, _P]),
     "cox_warp_shfl": (_I, [_P, _P, _I64, _I, C.c_int32, _P, _I, _P, _P]),
     "cox_warp_vote": (_I, [_P, _P, _I64, _P, _P, _P]),
+    "cox_tile_vote": (_I, [_P, _I64, _I, _P, _P, _P]),
     "cox_warp_reduce_blocks_i32": (_I, [_P, _I64, _P, _P, _P]),
     "cox_warp_reduce": (_I, [_P, _I, _I64, _I, C.POINTER(cox_cfg), _P, _P, _P, _SZ, _P]),
     "cox_warp_dot": (_I, [_P, _P, _I, _I64, _I, C.POINTER(cox_cfg), _P, _P, _P, _SZ, _P]),
@@ -215,6 +216,18 @@ def warp_vote(pred, mask=None):
         _need(mask, torch.int32, "mask")
     _check(lib().cox_warp_vote(_ptr(pred), _ptr(mask), pred.numel(), _ptr(bal), _ptr(aa), _stream()),
            "cox_warp_vote")
+    return bal, aa
+
+
+def tile_vote(pred, tile):
+    """Per tile of `tile` lanes: (T-bit ballot, any | all << 1) as int32
+    device tensors of n / tile entries."""
+    _need(pred, torch.int32, "pred")
+    g = pred.numel() // tile if tile > 0 else 0
+    bal = torch.zeros(g, dtype=torch.int32, device=pred.device)
+    aa = torch.zeros(g, dtype=torch.int32, device=pred.device)
+    _check(lib().cox_tile_vote(_ptr(pred), pred.numel(), int(tile), _ptr(bal), _ptr(aa), _stream()),
+           "cox_tile_vote")
     return bal, aa
 
 

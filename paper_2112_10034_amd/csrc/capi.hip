@@ -145,6 +145,22 @@ __global__ void k_warp_vote(const int32_t *__restrict__ pred, const uint32_t *__
   }
 }
 
+// Tile-scoped votes of thread_block_tile<T>: one element per lane; the
+// logical warp's ballot, shifted down to the lane's tile and cut to T bits,
+// is the tile's ballot; the tile's rank-0 lane stores it with any | all << 1.
+__global__ void k_tile_vote(const int32_t *__restrict__ pred, int64_t n, int T, uint32_t *__restrict__ ballot_out,
+                            int32_t *__restrict__ anyall) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;  // whole logical warps exit together (n % 32 == 0)
+  const int l = (int)(e & 31);
+  const uint32_t full = T == 32 ? FULL : (1u << T) - 1u;
+  const uint32_t b = (ballot(pred[e] != 0) >> (l & ~(T - 1))) & full;
+  if ((l & (T - 1)) == 0) {
+    ballot_out[e / T] = b;
+    anyall[e / T] = (b != 0u ? 1 : 0) | (b == full ? 2 : 0);
+  }
+}
+
 }  // namespace cox
 
 using namespace cox;
@@ -279,6 +295,17 @@ cox_status cox_warp_shfl(const int32_t *v, int32_t *out, int64_t n, int op, int3
   const int64_t grid = (n + 255) / 256;
   hipLaunchKernelGGL(k_warp_shfl, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, v, out, n,
                      op, (int)arg, argv, width, mask);
+  return launch_status();
+}
+
+cox_status cox_tile_vote(const int32_t *pred, int64_t n, int tile, uint32_t *ballot, int32_t *anyall,
+                         void *stream) {
+  if (n < 0 || n % 32 || !pow2_in(tile, 1, 32)) return COX_ERR_INVALID;
+  if (n == 0) return COX_OK;
+  if (!pred || !ballot || !anyall) return COX_ERR_INVALID;
+  const int64_t grid = (n + 255) / 256;
+  hipLaunchKernelGGL(k_tile_vote, dim3((unsigned)grid), dim3(256), 0, (hipStream_t)stream, pred, n, tile, ballot,
+                     anyall);
   return launch_status();
 }
 

@@ -28,6 +28,7 @@ int coxo_set_threads(int n);
 int coxo_warp_shfl(const int32_t *v, int32_t *out, int64_t n, int op, int32_t arg, const int32_t *argv,
                    int width, const uint32_t *mask);
 int coxo_warp_vote(const int32_t *pred, const uint32_t *mask, int64_t n, uint32_t *ballot, int32_t *anyall);
+int coxo_tile_vote(const int32_t *pred, int64_t n, int T, uint32_t *ballot, int32_t *anyall);
 int coxo_reduce_blocks_i32(const int32_t *x, int64_t n, int32_t *block_sums, int32_t *warp_pos);
 int coxo_reduce(const void *x, int dtype, int64_t n, int acc, int k, int W, void *partials, void *total);
 int coxo_dot(const void *a, const void *b, int dtype, int64_t n, int acc, int k, int W, void *partials,
@@ -211,8 +212,16 @@ static void case_vote(void) {
   expect(coxo_warp_vote(pred, NULL, n, bal, aa), OK, "vote");
   hmix(bal, n / 8), hmix(aa, n / 8);
   expect(coxo_warp_vote(pred, NULL, 31, bal, aa), INVALID, "vote");
+  uint32_t *tb = (uint32_t *)xalloc(n * 4);
+  int32_t *ta = (int32_t *)xalloc(n * 4);
+  for (int T = 1; T <= 32; T *= 2) {
+    expect(coxo_tile_vote(pred, n, T, tb, ta), OK, "tile vote");
+    hmix(tb, n / T * 4), hmix(ta, n / T * 4);
+  }
+  expect(coxo_tile_vote(pred, n, 3, tb, ta), INVALID, "tile vote");
+  expect(coxo_tile_vote(pred, 31, 1, tb, ta), INVALID, "tile vote");
   end("vote");
-  free(pred), free(mask), free(bal), free(aa);
+  free(pred), free(mask), free(bal), free(aa), free(tb), free(ta);
 }
 
 static void case_reduce_blocks(void) {

@@ -33,7 +33,7 @@ def test_header_declares_the_hot_path():
     names = declared_functions()
     for must in ["cox_warp_reduce", "cox_warp_scan", "cox_ballot_compact", "cox_tile_sort",
                  "cox_tile_reduce", "cox_warp_masked", "cox_warp_dot", "cox_warp_shfl",
-                 "cox_warp_vote", "cox_warp_reduce_blocks_i32"]:
+                 "cox_warp_vote", "cox_tile_vote", "cox_warp_reduce_blocks_i32"]:
         assert must in names
 
 
@@ -202,3 +202,15 @@ def test_noalloc_scan_rejects_sizes_beyond_its_scratch(cox):
     assert L.cox_warp_scan_noalloc(C.c_void_p((1 << 12) + 4), fake, 64, None, None, None) == 3
     bad = cox.make_cfg(3, 8)
     assert L.cox_warp_scan_noalloc(fake, fake, 64, C.byref(bad), None, None) != 0
+
+
+def test_tile_vote_rejects_bad_arguments(cox):
+    """Checked on the host before anything is launched."""
+    L = cox.lib()
+    fake = C.c_void_p(1 << 12)
+    for tile in (0, 3, 64):
+        assert L.cox_tile_vote(fake, 64, tile, fake, fake, None) == 1
+    assert L.cox_tile_vote(fake, 33, 4, fake, fake, None) == 1
+    assert L.cox_tile_vote(fake, -32, 4, fake, fake, None) == 1
+    assert L.cox_tile_vote(None, 64, 4, fake, fake, None) == 1
+    assert L.cox_tile_vote(None, 0, 4, None, None, None) == 0

@@ -82,6 +82,22 @@ def test_votes_random_masks(dev, oracle_mod):
     assert np.array_equal(down(ga), wa)
 
 
+@pytest.mark.parametrize("T", [1, 2, 4, 8, 16, 32])
+def test_tile_votes(dev, oracle_mod, T):
+    """Tile-scoped ballot / any / all against the oracle, predicates of
+    every density from all-false to all-true warps."""
+    torch, cox = dev
+    rng = np.random.default_rng(60 + T)
+    n = 32 * 20000
+    dens = np.repeat(rng.random(n // 1024), 1024)
+    pred = (rng.random(n) < dens).astype(np.int32) * rng.integers(-5, 6, n).astype(np.int32)
+    pred[:64] = np.repeat([0, 1], 32)
+    gb, ga = cox.tile_vote(up(torch, pred), T)
+    wb, wa = oracle_mod.tile_vote(pred, T)
+    assert np.array_equal(down(gb).view(np.uint32), wb)
+    assert np.array_equal(down(ga), wa)
+
+
 def test_paper_code1_and_code4_on_gpu(dev):
     torch, cox = dev
     val = torch.ones(32 * 4, dtype=torch.int32, device="cuda")

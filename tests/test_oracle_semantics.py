@@ -252,3 +252,50 @@ def test_empty_mask_vote_records_zero(oracle_mod):
     o = oracle_mod
     bal, aa = o.warp_vote(np.ones(32, np.int32), np.zeros(1, np.uint32))
     assert bal[0] == 0 and aa[0] == 0
+
+
+# ---------------------------------------------------------------- tile-scoped votes
+@pytest.mark.parametrize("T", [1, 2, 4, 8, 16, 32])
+def test_tile_votes_reassemble_the_warp_vote(oracle_mod, T):
+    """Pinned to the warp vote (itself pinned by Code 4): the T-bit ballots
+    of a warp's 32/T tiles, each shifted to its tile's first lane, OR to the
+    warp's full-mask ballot; any is the tile ballot being nonzero and all
+    the tile ballot being every one of its T bits.  At T = 32 the records
+    are the warp vote's."""
+    o = oracle_mod
+    rng = _rng(50 + T)
+    pred = (rng.random(32 * 500) < rng.random()).astype(np.int32) * rng.integers(-3, 4, 32 * 500).astype(np.int32)
+    pred[: 32 * 4] = np.repeat([0, 1, 0, 1], 32)  # all-false and all-true warps
+    tb, ta = o.tile_vote(pred, T)
+    wb, wa = o.warp_vote(pred)
+    per = 32 // T
+    shifted = tb.astype(np.uint64).reshape(-1, per) << (T * np.arange(per, dtype=np.uint64))
+    assert np.array_equal(np.bitwise_or.reduce(shifted, axis=1).astype(np.uint32), wb)
+    full = (1 << T) - 1
+    assert np.all(tb <= full)
+    assert np.array_equal(ta & 1, (tb != 0).astype(np.int32))
+    assert np.array_equal((ta >> 1) & 1, (tb == full).astype(np.int32))
+    if T == 32:
+        assert np.array_equal(tb, wb) and np.array_equal(ta, wa)
+
+
+def test_tile_votes_on_the_code4_predicate(oracle_mod):
+    """Code 4's predicate tx % 2 (odd lanes true): every tile of T >= 2
+    lanes has ballot 0b1010.. over its T bits, any true and all false;
+    tiles of one lane vote their own predicate."""
+    o = oracle_mod
+    pred = np.arange(256, dtype=np.int32) % 2
+    for T in (2, 4, 8, 16, 32):
+        tb, ta = o.tile_vote(pred, T)
+        assert np.all(tb == 0xAAAAAAAA & ((1 << T) - 1)), T
+        assert np.all(ta == 1), T
+    tb, ta = o.tile_vote(pred, 1)
+    assert np.array_equal(tb, pred.astype(np.uint32)) and np.array_equal(ta, pred * 3)
+
+
+def test_tile_vote_rejects_bad_tiles(oracle_mod):
+    for T in (0, 3, 64):
+        with pytest.raises(oracle_mod.OracleError, match="tile_vote"):
+            oracle_mod.tile_vote(np.zeros(64, np.int32), T)
+    with pytest.raises(oracle_mod.OracleError, match="tile_vote"):
+        oracle_mod.tile_vote(np.zeros(33, np.int32), 1)
