@@ -21,7 +21,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libcoxo.so")
+# COXO_LIB names another build of coxo.c (the mutation tests load
+# deliberately broken copies to show that the pins catch them)
+_LIB_PATH = os.environ.get("COXO_LIB") or os.path.join(_HERE, "libcoxo.so")
 
 I32, U32, F32, BF16 = 0, 1, 2, 3
 PLAIN, TWOSUM = 0, 1
