@@ -205,6 +205,22 @@ def test_segmented_fp_worked_example(dev, oracle_mod):
     assert np.array_equal(got[1].cpu().numpy().view(np.uint32), want.view(np.uint32))
 
 
+def test_segmented_fp_carry_kept_in_fp64(dev, oracle_mod):
+    """The oracle's three-chunk case whose carry leaves FP32's grid (2^24,
+    1, 1 in the first lanes of chunks of 32 at sigma = (1, 1)): the last
+    chunk outputs 2^24 + 2 and the total is 2^24 + 2 only if the look-back
+    carries and sums the chunk partials in FP64."""
+    torch, cox = dev
+    f = np.zeros(96, np.float32)
+    f[0], f[32], f[64] = 2.0 ** 24, 1.0, 1.0
+    off = np.array([0, 96], np.int64)
+    got = cox.segmented(torch.from_numpy(f).cuda(), torch.from_numpy(off).cuda(), 7, cfg=(1, 1))
+    check(torch, got, oracle_mod.segmented(f, off, 1, 1), 1)
+    want = np.repeat(np.array([2.0 ** 24, 2.0 ** 24, 2.0 ** 24 + 2], np.float32), 32)
+    assert np.array_equal(got[1].cpu().numpy().view(np.uint32), want.view(np.uint32))
+    assert got[0].cpu().item() == 2.0 ** 24 + 2
+
+
 def test_workspace_reuse_across_layouts(dev, oracle_mod):
     """Calls with different segment counts and schedules share the cached
     workspace, whose layout moves with them: each call must start from

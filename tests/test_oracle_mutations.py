@@ -3,8 +3,8 @@
 Each mutation below is a mistake someone could make while writing the
 oracle: a wrong element mapping, a missing or extra rounding, a wrong
 padding value, a reordered compensation, an off-by-one in a shuffle or
-scan bound, a wrong predicate, a flipped comparator, an unstable
-insertion.  It is applied to a scratch copy of coxo.c, built on the CPU
+scan bound, a wrong predicate or mask, a flipped comparator, an unstable
+insertion, an inverted step size, a misplaced output.  It is applied to a scratch copy of coxo.c, built on the CPU
 with the oracle's own flags, and the oracle's pin suites run against that
 build in a subprocess: at least one pin must fail.  (The committed oracle
 passes them all, in the rest of the test suite.)
@@ -17,7 +17,8 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "coxo.c")
-PINS = ["tests/test_oracle_kernels.py", "tests/test_oracle_semantics.py"]
+PINS = ["tests/test_oracle_kernels.py", "tests/test_oracle_semantics.py", "tests/test_oracle_image.py",
+        "tests/test_oracle_cg.py"]
 
 MUTATIONS = [
     ("bf16 rows of 4 elements instead of 8",
@@ -44,6 +45,29 @@ MUTATIONS = [
      "    while (j > 0 && k[j - 1] > kk) {", "    while (j > 0 && k[j - 1] >= kk) {"),
     ("row scan adds the shifted value one lane late",
      "      if ((l & 15) >= d) r[l] = sadd(isf, r[l], t[l]);", "      if ((l & 15) > d) r[l] = sadd(isf, r[l], t[l]);"),
+    ("masked operations take the density bound inclusively",
+     "  for (int l = 0; l < 32; l++) pr[l] = ((uint32_t)x[l] & 1023u) < (uint32_t)c->D;\n"
+     "  for (int l = 0; l < 32; l++) xch_put(&X, l, (uint64_t)pr[l]);",
+     "  for (int l = 0; l < 32; l++) pr[l] = ((uint32_t)x[l] & 1023u) <= (uint32_t)c->D;\n"
+     "  for (int l = 0; l < 32; l++) xch_put(&X, l, (uint64_t)pr[l]);"),
+    ("match_any leaves the calling lane out of its own set",
+     "    if (((mask >> i) & 1u) && x->v[i] == x->v[l]) r |= 1u << i;",
+     "    if (((mask >> i) & 1u) && i != l && x->v[i] == x->v[l]) r |= 1u << i;"),
+    ("integral image rows scanned exclusively",
+     "    s += c->img[y * c->W + x];\n    c->sat[y * c->W + x] = s;",
+     "    c->sat[y * c->W + x] = s;\n    s += c->img[y * c->W + x];"),
+    ("conjugate gradient beta as the inverse ratio",
+     "    g.coef = k == 0 ? 0.0f : (float)(rr / rr_prev);", "    g.coef = k == 0 ? 0.0f : (float)(rr_prev / rr);"),
+    ("conjugate gradient alpha as the inverse ratio",
+     "    g.coef = (float)(rr / pq);", "    g.coef = (float)(pq / rr);"),
+    ("segmented float scan carried in FP32",
+     "      if (isf) ((float *)c->y)[e0 + o] = (float)(fcarry + (double)q[o].f);",
+     "      if (isf) ((float *)c->y)[e0 + o] = (float)fcarry + q[o].f;"),
+    ("segmented compaction written from the start of out, not the segment's offset",
+     "    void *dst = isf ? (void *)((float *)c->outc + a + kept) : (void *)((int32_t *)c->outc + a + kept);",
+     "    void *dst = isf ? (void *)((float *)c->outc + kept) : (void *)((int32_t *)c->outc + kept);"),
+    ("segmented float totals rounded to FP32 per chunk",
+     "    if (isf) ftot = ftot + (double)P.s;", "    if (isf) ftot = (float)(ftot + (double)P.s);"),
 ]
 
 
