@@ -205,18 +205,22 @@ def test_segmented_fp_worked_example(dev, oracle_mod):
     assert np.array_equal(got[1].cpu().numpy().view(np.uint32), want.view(np.uint32))
 
 
-def test_segmented_fp_carry_kept_in_fp64(dev, oracle_mod):
+@pytest.mark.parametrize("k,W", [(1, 1), (32, 16)])
+def test_segmented_fp_carry_kept_in_fp64(dev, oracle_mod, k, W):
     """The oracle's three-chunk case whose carry leaves FP32's grid (2^24,
-    1, 1 in the first lanes of chunks of 32 at sigma = (1, 1)): the last
-    chunk outputs 2^24 + 2 and the total is 2^24 + 2 only if the look-back
-    carries and sums the chunk partials in FP64."""
+    1, 1 at the starts of chunks of S = 32kW elements; (32, 16) is the
+    10,000-segment workload's tuned schedule): the last chunk outputs
+    2^24 + 2 and the total is 2^24 + 2 only if the look-back carries and
+    sums the chunk partials in FP64."""
     torch, cox = dev
-    f = np.zeros(96, np.float32)
-    f[0], f[32], f[64] = 2.0 ** 24, 1.0, 1.0
-    off = np.array([0, 96], np.int64)
-    got = cox.segmented(torch.from_numpy(f).cuda(), torch.from_numpy(off).cuda(), 7, cfg=(1, 1))
-    check(torch, got, oracle_mod.segmented(f, off, 1, 1), 1)
-    want = np.repeat(np.array([2.0 ** 24, 2.0 ** 24, 2.0 ** 24 + 2], np.float32), 32)
+    S = 32 * k * W
+    f = np.zeros(3 * S, np.float32)
+    f[0], f[S], f[2 * S] = 2.0 ** 24, 1.0, 1.0
+    off = np.array([0, 3 * S], np.int64)
+    print("segmented fp64 carry, sigma", k, W, flush=True)
+    got = cox.segmented(torch.from_numpy(f).cuda(), torch.from_numpy(off).cuda(), 7, cfg=(k, W))
+    check(torch, got, oracle_mod.segmented(f, off, k, W), 1)
+    want = np.repeat(np.array([2.0 ** 24, 2.0 ** 24, 2.0 ** 24 + 2], np.float32), S)
     assert np.array_equal(got[1].cpu().numpy().view(np.uint32), want.view(np.uint32))
     assert got[0].cpu().item() == 2.0 ** 24 + 2
 

@@ -734,21 +734,24 @@ def test_segmented_fp_scan_worked_example(oracle_mod):
     assert np.array_equal(cnt, [32, 64]) and np.array_equal(oc, f)
 
 
-def test_segmented_fp_carry_and_total_kept_in_fp64(oracle_mod):
+@pytest.mark.parametrize("k,W", [(1, 1), (32, 16)])
+def test_segmented_fp_carry_and_total_kept_in_fp64(oracle_mod, k, W):
     """A hand-derived case where the running chunk carry leaves FP32's
-    grid, at sigma = (1, 1) (32 elements per chunk): one segment of three
-    chunks holding 2^24, 1 and 1 in their first lanes and zeros elsewhere.
+    grid, with S = 32kW elements per chunk (32 at sigma = (1, 1), 16384 at
+    (32, 16)): one segment of three chunks holding 2^24, 1 and 1 in their
+    first elements and zeros elsewhere.
     Each chunk's scan is exact (it adds only zeros), so chunk 0 outputs
     2^24; chunk 1 outputs (float)(2^24 + 1), a tie that rounds to the even
     2^24; chunk 2's carry is the FP64 sum 2^24 + 1, so it outputs
     (float)(2^24 + 2) = 2^24 + 2.  A carry kept in FP32 would hold 2^24
     there and give 2^24 again.  The segment total is the FP64 sum of the
     chunk partials, 2^24 + 2; rounding it to FP32 per chunk gives 2^24."""
-    f = np.zeros(96, np.float32)
-    f[0], f[32], f[64] = 2.0 ** 24, 1.0, 1.0
-    off = np.array([0, 96], np.int64)
-    tot, y, oc, cnt = oracle_mod.segmented(f, off, 1, 1)
-    want = np.repeat(np.array([2.0 ** 24, 2.0 ** 24, 2.0 ** 24 + 2], np.float32), 32)
+    S = 32 * k * W
+    f = np.zeros(3 * S, np.float32)
+    f[0], f[S], f[2 * S] = 2.0 ** 24, 1.0, 1.0
+    off = np.array([0, 3 * S], np.int64)
+    tot, y, oc, cnt = oracle_mod.segmented(f, off, k, W)
+    want = np.repeat(np.array([2.0 ** 24, 2.0 ** 24, 2.0 ** 24 + 2], np.float32), S)
     assert np.array_equal(y.view(np.uint32), want.view(np.uint32))
     assert tot[0] == 2.0 ** 24 + 2
     assert cnt[0] == 3 and np.array_equal(oc[:3], [2.0 ** 24, 1.0, 1.0])
