@@ -355,6 +355,23 @@ def test_tile_reduce_unaligned_input(dev, oracle_mod, T):
     assert np.array_equal(got, oracle_mod.tile_reduce_i32(x[1:], T))
 
 
+@pytest.mark.parametrize("T", [4, 8, 16, 32])
+def test_tile_reduce_unaligned_output(dev, oracle_mod, T):
+    """out starting 4 bytes past a 16-byte boundary: tiles of 8 and 16 then
+    store one sum per tile instead of 16-byte vectors.  The words around
+    the output stay untouched."""
+    torch, cox = dev
+    n = 2048 * 40 + 96
+    x = inputs.masked_input(n)
+    nt = (n + T - 1) // T
+    buf = torch.full((nt + 8,), -7, dtype=torch.int32, device="cuda")
+    got = cox.tile_reduce(up(torch, x), T, out=buf[1:1 + nt])
+    assert got.data_ptr() % 16 == 4
+    b = down(buf)
+    assert np.array_equal(b[1:1 + nt], oracle_mod.tile_reduce_i32(x, T))
+    assert b[0] == -7 and np.all(b[1 + nt:] == -7)
+
+
 @pytest.mark.parametrize("D", (0, 1, 102, 512, 922, 1024))
 def test_masked_ops(dev, oracle_mod, D):
     torch, cox = dev
