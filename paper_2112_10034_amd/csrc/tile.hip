@@ -71,7 +71,7 @@ __global__ __launch_bounds__(256) void k_tile_reduce(const int32_t *__restrict__
       const int64_t e = base + r * 1024 + 4 * t;  // first element of the lane
       uint32_t a, b;
       tile_sums<T>(v[r], a, b);
-      if constexpr (T == 8 || T == 16) {
+      if constexpr (T >= 4 && T <= 16) {
         // every lane of a tile holds its sum; in a full round the first lane
         // of four consecutive tiles takes the other three from lanes G, 2G
         // and 3G further on (all in its 16-lane row) and writes the four as
@@ -227,13 +227,13 @@ cox_status cox_tile_reduce(const int32_t *x, int64_t n, int tile, int32_t *out, 
   if (n == 0) return COX_OK;
   if (!x || !out) return COX_ERR_INVALID;
   // two rows of 1024 elements per block and round, four blocks per compute
-  // unit (eight for tiles of 2 and 4), measured over 2^26 elements after a
-  // cache scrub: 45.9 / 50.8 / 55.9 / 61.8 us for T = 32 / 16 / 8 / 4
-  // against 48.6 / 52.7 / 57.9 / 62.4 us with four rows and four blocks.
-  // Tiles of 8 and 16 write their sums as 16-byte vectors into an aligned
-  // out (48.0 / 51.7 us against 51.1 / 55.4 with one 4-byte store per tile;
-  // slower for tiles of 4, whose output is a quarter of the input)
-  const int grid = persistent_grid((const void *)fn, 256, (n + 1024 * 2 - 1) / (1024 * 2), 0, 0, tile <= 4 ? 8 : 4);
+  // unit (eight for tiles of 2), measured over 2^26 elements after a cache
+  // scrub: 45.9 / 50.8 / 55.9 us for T = 32 / 16 / 8 against 48.6 / 52.7 /
+  // 57.9 us with four rows.  Tiles of 4, 8 and 16 write their sums as
+  // 16-byte vectors into an aligned out: 58.3 / 52.3 / 47.2 us against
+  // 61.8 / 55.5 / 51.0 with one 4-byte store per tile (tiles of 4 with
+  // eight blocks per compute unit: 64.1 us)
+  const int grid = persistent_grid((const void *)fn, 256, (n + 1024 * 2 - 1) / (1024 * 2), 0, 0, tile <= 2 ? 8 : 4);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, x, n, out, aligned16(out));
   return launch_status();
 }
