@@ -381,3 +381,19 @@ def test_masked_ops(dev, oracle_mod, D):
     oo, orec = oracle_mod.warp_masked(x, D)
     assert np.array_equal(down(out), oo)
     assert np.array_equal(down(rec).view(np.uint32), orec)
+
+
+@pytest.mark.parametrize("D", (102, 922))
+def test_masked_ops_unaligned_output(dev, oracle_mod, D):
+    """out starting 4 bytes past a 16-byte boundary takes one store per
+    lane instead of 16-byte vectors; the words around it stay untouched."""
+    torch, cox = dev
+    n = 32 * 20011
+    x = inputs.masked_input(n)
+    buf = torch.full((n + 8,), -7, dtype=torch.int32, device="cuda")
+    out, rec = cox.warp_masked(up(torch, x), D, out=buf[1:1 + n])
+    assert out.data_ptr() % 16 == 4
+    oo, orec = oracle_mod.warp_masked(x, D)
+    b = down(buf)
+    assert np.array_equal(b[1:1 + n], oo) and b[0] == -7 and np.all(b[1 + n:] == -7)
+    assert np.array_equal(down(rec).view(np.uint32), orec)
