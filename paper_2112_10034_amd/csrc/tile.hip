@@ -6,14 +6,17 @@
 // consecutive elements per round (coalesced streaming 4-byte loads, R loads
 // in flight per thread), and the whole block runs every round so that the
 // exchanges always see full warps (16 rows per round, eight blocks per
-// compute unit).
+// compute unit).  Into a 16-byte aligned output, each group of four lanes
+// writes its four outputs as one streaming 16-byte vector.
 //
 // Tile reductions are int32 sums modulo 2^32, whose value does not depend
 // on the order of the additions, so the kernel loads 16-byte vectors: a
 // lane holds 4 consecutive elements, adds them, and a tile of T elements is
 // finished by the xor exchanges of the T/4 lanes holding it -- the same bits
-// as the one-element-per-lane shfl_down tree.  The default grid is four
-// 256-thread blocks per compute unit.
+// as the one-element-per-lane shfl_down tree.  A block takes two rows of
+// 1024 elements per round, four 256-thread blocks per compute unit (eight
+// for tiles of 2); tiles of 4, 8 and 16 write four consecutive sums as one
+// streaming 16-byte vector into an aligned output.
 #include "cox_internal.hpp"
 
 namespace cox {
@@ -22,7 +25,7 @@ namespace cox {
 typedef uint32_t u32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
 // the lanes of a tile hold T/4 x 4 consecutive elements: in-lane sum, then
-// xor exchanges inside the T/4-lane group (its first lane ends with the sum)
+// xor exchanges inside the T/4-lane group (every lane of it ends with the sum)
 template <int T>
 __device__ __forceinline__ void tile_sums(const uint32_t (&v)[4], uint32_t &a, uint32_t &b) {
   if constexpr (T == 2) {
