@@ -414,11 +414,11 @@ extern "C" cox_status cox_tile_sort(const uint32_t *keys, uint32_t *out, int64_t
   const int64_t nvec = (n + k - 1) / k;
   const int U = k >= 16 ? 1 : 16 / k > 4 ? 4 : 16 / k;
   // default blocks per compute unit (measured at 2^28 keys): two for
-  // 32-key groups and for 64-key groups with several keys per lane; eight
-  // for wider groups and for 64 keys over a full wave, whose longer
-  // networks need more waves in flight (1024-key groups: 0.69 ms against
-  // 0.95 ms with two)
-  const int per_cu = tile == 32 || (k >= 2 && tile <= 64) ? 2 : 8;
+  // 32-key groups and for 64-key groups with several keys per lane; six
+  // for 64 keys over a full wave (0.420 ms against 0.434 with eight); eight
+  // for wider groups, whose longer networks need more waves in flight
+  // (1024-key groups: 0.69 ms against 0.95 ms with two)
+  const int per_cu = tile == 32 || (k >= 2 && tile <= 64) ? 2 : tile == 64 ? 6 : 8;
   const int grid = persistent_grid((const void *)fn, 256, (nvec + 256 * U - 1) / (256 * U),
                                    cfg ? cfg->grid_blocks : 0, 0, per_cu);
   hipLaunchKernelGGL(fn, dim3(grid), dim3(256), 0, (hipStream_t)stream, keys, out, n);
